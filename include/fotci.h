@@ -1,0 +1,225 @@
+/*
+ * fotci -- factorized on-the-fly configuration interaction on MI355X (gfx950).
+ *
+ * C-ABI of the library (libfotci.so). The library computes the Hamiltonian
+ * times a vector in the M-scheme basis of proton Slater determinants (SDs)
+ * times neutron SDs, reconstructing matrix elements on the fly from
+ * precomputed one-species "jumps", and the lowest eigenvalues of H by Lanczos
+ * with full reorthogonalisation.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value 0 = success; a negative FOTCI_E* code on failure, with a
+ *    message from fotci_last_error() (thread-local; valid until the next call
+ *    on the same thread). No C++ exception crosses the ABI.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are GPU
+ *    memory owned by the caller (e.g. a torch tensor's data_ptr()). The
+ *    library never allocates device memory: the caller passes workspaces of
+ *    the size the matching *_bytes query returns.
+ *  - stream arguments are hipStream_t passed as void* (NULL = null stream).
+ *    Device work is enqueued asynchronously unless a call says otherwise.
+ *  - Handles (fotci_basis, fotci_jumps, fotci_ham) are library-owned host
+ *    objects, released with the matching fotci_free_*; a fotci_jumps keeps
+ *    its fotci_basis alive by reference, so free in reverse order of creation.
+ */
+#ifndef FOTCI_H
+#define FOTCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FOTCI_OK 0
+#define FOTCI_EINVAL (-1)    /* invalid argument or inconsistent input */
+#define FOTCI_ENOMEM (-2)    /* workspace too small / host allocation failed */
+#define FOTCI_EHIP (-3)      /* a HIP runtime call or kernel launch failed */
+#define FOTCI_ENOTCONV (-4)  /* Lanczos could not produce the requested states */
+#define FOTCI_ESTATE (-5)    /* call out of order (e.g. apply before upload) */
+
+/* Arithmetic modes of apply_H / lanczos_lowest. */
+#define FOTCI_MODE_F64_PLAIN 0  /* float64 vectors; straightforward gather kernel */
+#define FOTCI_MODE_F64 1        /* float64 vectors; tiled kernels */
+#define FOTCI_MODE_F32 2        /* float32 vectors and matrix elements */
+#define FOTCI_MODE_BF16X3 3     /* float32 vectors; pn contraction on bf16 MFMA, 3-term split */
+
+/* Jump kinds for fotci_jumps_count / fotci_jumps_export. */
+#define FOTCI_JUMP_PP2 0  /* proton two-body jumps */
+#define FOTCI_JUMP_NN2 1  /* neutron two-body jumps */
+#define FOTCI_JUMP_P1 2   /* proton one-body jumps */
+#define FOTCI_JUMP_N1 3   /* neutron one-body jumps */
+
+typedef struct fotci_basis fotci_basis;
+typedef struct fotci_jumps fotci_jumps;
+typedef struct fotci_ham fotci_ham;
+
+const char *fotci_last_error(void);
+const char *fotci_version(void);
+
+/*
+ * fotci_build_basis -- the factorised M-scheme basis (Ch. 2, "Use of quantum
+ * numbers: factorization of the basis"; Ch. 6, "Writing out the basis").
+ *
+ *  n_orbits, two_j[n_orbits], parity[n_orbits] (host): the single-particle
+ *    orbits, identical for protons and neutrons; 2j odd and > 0, parity +1 or
+ *    -1. m-states are numbered orbit by orbit, 2m ascending inside an orbit;
+ *    m-state i is bit i of an SD mask, so the total N_s must be <= 32.
+ *  Z, N: valence protons and neutrons (0 <= Z, N <= N_s).
+ *  two_M: twice the total Jz; its parity must equal that of Z + N.
+ *  parity_total: +1 or -1.
+ *  Proton sectors are ordered by 2M_p ascending (parity +1 before -1); a
+ *  species sector whose conjugate sector is empty is dropped; SDs inside a
+ *  sector ascend by mask value; basis index = pstart[ip] + nstart[jn] with
+ *  the neutron index fastest.
+ *  *out receives a new handle. FOTCI_EINVAL on bad arguments or an empty
+ *  basis.
+ */
+int fotci_build_basis(int32_t n_orbits, const int32_t *two_j, const int32_t *parity,
+                      int32_t Z, int32_t N, int32_t two_M, int32_t parity_total,
+                      fotci_basis **out);
+void fotci_free_basis(fotci_basis *b);
+
+/* Sizes of the basis (any output pointer may be NULL). */
+int fotci_basis_info(const fotci_basis *b, int64_t *dim, int32_t *n_sectors,
+                     int32_t *n_psd, int32_t *n_nsd, int32_t *n_states);
+
+/*
+ * fotci_basis_export -- copy the basis tables into caller-allocated host
+ * arrays (any may be NULL): p_bits[n_psd], n_bits[n_nsd] (SD masks in basis
+ * order), pstart[n_psd], nstart[n_nsd], and sector_table[n_sectors*7] with
+ * rows (2M_p, parity_p, first pSD, #pSDs, first nSD, #nSDs, offset).
+ */
+int fotci_basis_export(const fotci_basis *b, uint32_t *p_bits, uint32_t *n_bits,
+                       int64_t *pstart, int64_t *nstart, int64_t *sector_table);
+
+/*
+ * fotci_build_jumps -- one-species jumps (Ch. 2, "Representation of the
+ * Hamiltonian"; Ch. 8, "Opbundles and optypes"): the nonzero results of
+ * p+_a p+_b p_d p_c (two-body; a<b, c<d conserving 2M and parity, diagonal
+ * included; label = pair(a,b) * n_pairs + pair(c,d), pairs (a<b) numbered
+ * lexicographically) and of p+_a p_c (one-body; any a, c; label = a*N_s + c;
+ * the destination must be a kept SD) on every kept SD of each species, with
+ * the fermion phase (-1)^(occupied states below the index) of each operator.
+ * The basis must outlive the jumps.
+ */
+int fotci_build_jumps(const fotci_basis *b, fotci_jumps **out);
+void fotci_free_jumps(fotci_jumps *j);
+
+/* Number of records of one kind (FOTCI_JUMP_*). */
+int fotci_jumps_count(const fotci_jumps *j, int32_t kind, int64_t *count);
+
+/*
+ * Copy one kind's records, sorted by (dst, src, label), into caller-allocated
+ * host arrays of length count (any may be NULL). src/dst are species SD
+ * indices in basis order; phase is +1 or -1.
+ */
+int fotci_jumps_export(const fotci_jumps *j, int32_t kind, int32_t *src, int32_t *dst,
+                       int8_t *phase, int32_t *label);
+
+/*
+ * fotci_set_interaction -- the one- plus two-body Hamiltonian in M-scheme
+ * form (Ch. 11, "The Hamiltonian and other operators in second
+ * quantization", eq. hamdef, with V already uncoupled):
+ *   H = sum_i eps_p[orb i] n_i(p) + sum_i eps_n[orb i] n_i(n)
+ *     + sum_{a<b,c<d} v_pp[(ab),(cd)] p+_a p+_b p_d p_c   (v_nn alike)
+ *     + sum_{abcd} v_pn[(a b),(c d)] (p+_a p_c)(n+_b n_d).
+ *  spe_p, spe_n: host [n_orbits]; v_pp, v_nn: host [n_pairs*n_pairs]
+ *  row-major; v_pn: host [(N_s*N_s)^2], row index a*N_s+b (proton a,
+ *  neutron b). Arrays are copied. Every array must be exactly symmetric and
+ *  zero wherever 2M or parity would change, else FOTCI_EINVAL. The jumps must
+ *  outlive the Hamiltonian.
+ */
+int fotci_set_interaction(const fotci_jumps *j, const double *spe_p, const double *spe_n,
+                          const double *v_pp, const double *v_nn, const double *v_pn,
+                          fotci_ham **out);
+void fotci_free_ham(fotci_ham *h);
+
+/* Replace the interaction values (same rules as fotci_set_interaction). If
+ * the Hamiltonian is uploaded, the device copy is refreshed on `stream`. */
+int fotci_ham_set_values(fotci_ham *h, const double *spe_p, const double *spe_n,
+                         const double *v_pp, const double *v_nn, const double *v_pn,
+                         void *stream);
+
+/* Bytes of device workspace fotci_ham_upload needs (>= 0), or a negative code. */
+int64_t fotci_ham_workspace_bytes(const fotci_ham *h);
+
+/*
+ * fotci_ham_upload -- copy the jump tables and interaction into the
+ * caller-owned device workspace (256-byte aligned, `bytes` >= the size from
+ * fotci_ham_workspace_bytes, else FOTCI_ENOMEM) and form the per-jump matrix
+ * element values on the device. The workspace must stay allocated and
+ * untouched while the Hamiltonian is used. Synchronises `stream` before
+ * returning.
+ */
+int fotci_ham_upload(fotci_ham *h, void *dev_workspace, int64_t bytes, void *stream);
+
+/*
+ * fotci_apply_H -- y = H x (overwrite), the on-the-fly matrix-vector product
+ * (Ch. 2, "Representation of the Hamiltonian"; Ch. 8, "Mode times": pp, nn
+ * and pn parts plus single-particle energies). x, y: device vectors of length
+ * dim in basis order, float64 for the F64 modes and float32 otherwise; x and
+ * y must not overlap. Asynchronous on `stream`.
+ */
+int fotci_apply_H(const fotci_ham *h, int32_t mode, const void *x, void *y, void *stream);
+
+/*
+ * fotci_apply_H_vjp -- adjoint of y = H(v) x for L = <g, y> (float64 only):
+ *   dx = H g  (H is symmetric), written to dx (device, length dim) if non-NULL;
+ *   d_v_pp[(ab),(cd)] += <g| p+_a p+_b p_d p_c |x>  (device [n_pairs^2]), and
+ *   d_v_nn, d_v_pn [(N_s^2)^2] alike, d_spe_p/d_spe_n [n_orbits] += <g|n_orbit|x>:
+ *   the label-wise transition densities (Ch. 5, "Two-body densities").
+ * Gradient buffers are accumulated into (the caller zeroes them); each may be
+ * NULL. Entries (r,c) and (c,r) are separate (unsymmetrised).
+ */
+int fotci_apply_H_vjp(const fotci_ham *h, const double *x, const double *g, double *dx,
+                      double *d_spe_p, double *d_spe_n, double *d_v_pp, double *d_v_nn,
+                      double *d_v_pn, void *stream);
+
+typedef struct {
+    int32_t n_keep;   /* number of lowest eigenpairs wanted (>= 1) */
+    int32_t n_iter;   /* Lanczos iterations (Krylov dimension), n_keep <= n_iter */
+    int32_t mode;     /* FOTCI_MODE_*: storage/arithmetic of vectors and apply_H */
+    int32_t refine;   /* 1: float64 Rayleigh-quotient refinement of the Ritz vectors */
+} fotci_lanczos_opts;
+
+/* Bytes of device workspace fotci_lanczos_lowest needs for these options. */
+int64_t fotci_lanczos_workspace_bytes(const fotci_ham *h, const fotci_lanczos_opts *o);
+
+/*
+ * fotci_lanczos_lowest -- lowest eigenvalues by Lanczos with full
+ * reorthogonalisation (Ch. 7, "Standard Lanczos algorithm": alpha first, then
+ * classical Gram-Schmidt twice against every earlier vector, float64
+ * accumulation). Lanczos vectors are stored in the mode's precision; alpha,
+ * beta, reorthogonalisation coefficients and the tridiagonal eigenproblem are
+ * float64.
+ *  pivot: device float64 [dim], the starting vector (normalised internally).
+ *  work: device workspace of the queried size (FOTCI_ENOMEM if smaller).
+ *  evals, resid: host [n_keep]; resid = ||H y - theta y|| / ||y|| in float64.
+ *  evecs: device float64 [n_keep*dim] Ritz vectors (unit norm), or NULL.
+ *  alpha, beta: host [n_iter] copies of the recurrence, or NULL.
+ * With refine = 1, theta is the float64 Rayleigh quotient of each Ritz vector.
+ * Synchronous (returns after the stream drained). FOTCI_ENOTCONV when the
+ * Krylov space breaks down before n_keep Ritz values exist.
+ */
+int fotci_lanczos_lowest(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot,
+                         void *work, int64_t work_bytes, double *evals, double *resid,
+                         double *evecs, double *alpha, double *beta, void *stream);
+
+/* Counts of the work in one apply_H (host; no device needed): multiply-adds
+ * of the pp, nn and pn parts and of the diagonal, as the paper counts
+ * "operations" (Ch. 8, "Jump storage"). */
+int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn,
+                        int64_t *ops_diag);
+
+/*
+ * Host utility: eigenvalues (ascending) and orthonormal eigenvectors of the
+ * symmetric tridiagonal matrix with diagonal diag[n] and off-diagonal
+ * offdiag[n-1] in float64 (the tridiagonal step of Lanczos; implicit QL).
+ * evecs: host [n*n] row-major, column k = eigenvector k, or NULL.
+ */
+int fotci_tridiag_eigh(int32_t n, const double *diag, const double *offdiag, double *evals, double *evecs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOTCI_H */

@@ -178,8 +178,8 @@ def densities(b, g, x):
     return out
 
 
-def jumps(b, species):
-    """Jump lists of one species over its kept SDs.
+def jumps(b, species, src_subset=None):
+    """Jump lists of one species over its kept SDs (or only from ``src_subset``).
 
     Returns dict with 'two_body' and 'one_body', each an int64 array of rows
     (src, dst, phase, label) sorted by (dst, src, label):
@@ -197,7 +197,9 @@ def jumps(b, species):
     npairs = len(pl)
     pidx = {p: k for k, p in enumerate(pl)}
     two, one = [], []
-    for src, mask in enumerate(sds):
+    srcs = range(len(sds)) if src_subset is None else sorted(int(i) for i in src_subset)
+    for src in srcs:
+        mask = sds[src]
         occ = _occ(mask, ns)
         for i1 in range(len(occ)):
             for i2 in range(i1 + 1, len(occ)):

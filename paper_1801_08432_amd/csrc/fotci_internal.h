@@ -1,0 +1,195 @@
+// Internal types of libfotci: host-side basis, jumps and Hamiltonian tables,
+// and the device view the kernels read.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fotci.h"
+
+namespace fotci {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_error(const std::string &msg);
+
+// -------------------------------------------------------------- m-states
+struct MState {
+    int orbit, two_j, two_m, parity;
+};
+
+// One species' kept SDs, grouped into (2M, parity) sectors.
+struct SpeciesBasis {
+    int n = 0;                       // particles
+    std::vector<uint32_t> sd;        // kept SD masks, basis order
+    std::vector<int32_t> sd_sector;  // species sector of each SD
+    std::vector<int32_t> sd_local;   // rank inside its species sector
+    struct Sector {
+        int two_m, parity, first, count;
+    };
+    std::vector<Sector> sectors;
+    // index of a mask among the kept SDs, or -1
+    int32_t find(uint32_t mask, const std::vector<MState> &ms) const;
+};
+
+struct BasisSector {
+    int two_mp, parity_p;
+    int p_sector, n_sector;          // species sector indices
+    int p_first, np, n_first, nn;
+    int64_t offset;
+};
+
+}  // namespace fotci
+
+struct fotci_basis {
+    std::vector<fotci::MState> ms;
+    int n_orbits = 0;
+    int two_M = 0, parity = 1;
+    fotci::SpeciesBasis p, n;
+    std::vector<fotci::BasisSector> sectors;
+    std::vector<int32_t> p_basis_sector;   // per proton SD: basis sector
+    std::vector<int64_t> pstart, nstart;
+    int64_t dim = 0;
+};
+
+namespace fotci {
+
+struct JumpRec {
+    int32_t src, dst;
+    int32_t label;
+    int8_t phase;
+};
+
+// One-body operator classes: a+_a a_c grouped by (Delta = 2m_a - 2m_c,
+// rho = parity_a * parity_c). A proton class q pairs with the neutron class
+// conj[q] of opposite Delta and the same rho.
+struct OpClasses {
+    int nq = 0;
+    std::vector<int> delta, rho, conj;
+    std::vector<std::vector<int>> ops;   // labels a*ns+c in the class, ascending
+    std::vector<int> class_of;           // label -> class
+    std::vector<int> local_of;           // label -> position in its class
+};
+
+}  // namespace fotci
+
+struct fotci_jumps {
+    const fotci_basis *b = nullptr;
+    int ns = 0, npairs = 0;
+    std::vector<fotci::JumpRec> rec[4];  // FOTCI_JUMP_* order, canonical sort
+    fotci::OpClasses cls;
+};
+
+namespace fotci {
+
+// Device-side view of one species' tables.
+struct DevSpecies {
+    const uint32_t *masks;     // [n_sd]
+    const int32_t *code2;      // [n_jump2] two-body jump codes: label*2 + (phase<0)
+    const int32_t *off_rowptr; // [n_sd+1] off-diagonal merged entries by dst
+    const int32_t *off_col;    // [n_off] source SD
+    const int32_t *off_j0;     // [n_off] jump range of the entry
+    const int32_t *off_j1;
+    const int32_t *diag_j0;    // [n_sd] diagonal jump range (j0 == j1: none)
+    const int32_t *diag_j1;
+    const int32_t *ob_ptr;     // [n_sd*nq+1] one-body jumps by (dst, class)
+    const int32_t *ob_src;     // [n_ob] source SD
+    const int32_t *ob_code;    // [n_ob] local op index*2 + (phase<0)
+    const double *eps;         // [ns] single-particle energy per m-state
+    const double *v2;          // [npairs^2] two-body matrix elements
+    double *off_val64;         // [n_off] merged matrix elements
+    float *off_val32;
+    double *d64;               // [n_sd] diagonal: spe + diagonal two-body
+    float *d32;
+    int32_t n_sd, n_off;
+};
+
+struct DevHam {
+    int32_t ns, npairs, nq, n_sectors;
+    int32_t n_vq;              // length of the blocked pn element array
+    int64_t dim;
+    const int32_t *p_sector;   // [n_psd] basis sector of each proton SD
+    const int64_t *p_pstart;   // [n_psd]
+    const int32_t *n_local;    // [n_nsd] nstart
+    const int32_t *sec_nn;     // [n_sectors]
+    const int32_t *sec_nfirst; // [n_sectors]
+    const int32_t *sec_pfirst; // [n_sectors]
+    const int32_t *sec_np;     // [n_sectors]
+    const int64_t *sec_off;    // [n_sectors]
+    const int32_t *conjq;      // [nq]
+    const int32_t *ms_orbit;   // [ns] orbit of each m-state
+    const int32_t *n_bsector;  // [n_nsd] basis sector of each neutron SD
+    const int32_t *cls_off;    // [nq+1] class q's op labels are cls_ops[cls_off[q]..cls_off[q+1])
+    const int32_t *cls_ops;    // [ns*ns] op labels a*ns+c grouped by class
+    const int32_t *vq_off;     // [nq] offset of V^q in vq64/vq32
+    const int32_t *vq_nb;      // [nq] columns of V^q (= #ops of the neutron class)
+    const double *vq64;
+    float *vq32;
+    double *scratch_ncol;      // [n_nsd] adjoint scratch: per-neutron-SD column sums
+    DevSpecies p, n;
+};
+
+// Host-side tables (built once per jumps + interaction layout).
+struct HostCommonTables {
+    std::vector<int32_t> p_sector, n_local, sec_nn, sec_nfirst, sec_pfirst, sec_np, conjq;
+    std::vector<int32_t> ms_orbit, n_bsector, cls_off, cls_ops;
+    std::vector<int64_t> sec_off;
+};
+
+struct HostSpeciesTables {
+    std::vector<uint32_t> masks;
+    std::vector<int32_t> code2, off_rowptr, off_col, off_j0, off_j1, diag_j0, diag_j1;
+    std::vector<int32_t> ob_ptr, ob_src, ob_code;
+    std::vector<double> eps, v2;
+};
+
+}  // namespace fotci
+
+struct fotci_ham {
+    const fotci_jumps *j = nullptr;
+    std::vector<double> spe_p, spe_n, v_pp, v_nn, v_pn;
+    std::vector<double> vq;               // blocked pn matrix elements
+    std::vector<int32_t> vq_off, vq_nb;
+    fotci::HostSpeciesTables tp, tn;
+    fotci::HostCommonTables tc;
+    // device
+    bool uploaded = false;
+    void *ws = nullptr;
+    int64_t ws_bytes = 0;
+    fotci::DevHam dev{};
+    // layout (offsets in bytes from ws), filled by layout()
+    std::vector<std::pair<std::string, int64_t>> layout_offsets;
+    int64_t layout_total = 0;
+};
+
+namespace fotci {
+// host helpers
+int pair_index(int a, int b, int ns);
+void build_species_tables(const fotci_jumps *j, int species, HostSpeciesTables &t);
+void block_pn(fotci_ham *h);
+void fill_species_values(fotci_ham *h);
+
+// device helpers (kernels_*.hip)
+void launch_materialize(const DevHam &d, void *stream);
+void launch_apply(const DevHam &d, int mode, const void *x, void *y, void *stream);
+void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g,
+                double *dx, double *d_spe_p, double *d_spe_n, double *d_v_pp, double *d_v_nn,
+                double *d_v_pn, void *stream);
+int64_t lanczos_bytes(const fotci_ham *h, const fotci_lanczos_opts *o);
+void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, void *work,
+                 int64_t work_bytes, double *evals, double *resid, double *evecs, double *alpha,
+                 double *beta, void *stream);
+void hip_check(int err, const char *what);
+
+// tridiagonal symmetric eigenproblem (host, float64): implicit QL with
+// Wilkinson shifts; eigenvalues ascending in d, eigenvectors in z (n x n,
+// column k = eigenvector k, row-major storage z[i*n+k]).
+void launch_apply_any(const fotci_ham *h, int mode, const void *x, void *y, void *stream);
+void tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, std::vector<double> &z);
+
+}  // namespace fotci

@@ -1,0 +1,369 @@
+// Host side of the Hamiltonian: validation of the interaction, the device
+// table layout (jumps grouped for destination-ordered gathers, pn matrix
+// elements blocked by one-body operator class) and the upload into the
+// caller's workspace.
+//
+// Matrix-element reconstruction follows Ch. 2 "Representation of the
+// Hamiltonian": a pp (nn) matrix element is the sum, over the proton
+// (neutron) two-body jumps between the same pair of SDs, of phase x V[label];
+// a pn matrix element is phase_p x phase_n x V_pn for a pair of one-body
+// jumps whose Jz changes cancel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fotci_internal.h"
+
+namespace fotci {
+
+void hip_check(int err, const char *what) {
+    if (err != hipSuccess) fail(FOTCI_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)err));
+}
+
+void build_species_tables(const fotci_jumps *j, int sp, HostSpeciesTables &t) {
+    const fotci_basis *b = j->b;
+    const SpeciesBasis &S = sp == 0 ? b->p : b->n;
+    const int n_sd = (int)S.sd.size();
+    t.masks = S.sd;
+    const auto &two = j->rec[sp == 0 ? FOTCI_JUMP_PP2 : FOTCI_JUMP_NN2];
+    t.code2.resize(two.size());
+    t.off_rowptr.assign(n_sd + 1, 0);
+    t.off_col.clear();
+    t.off_j0.clear();
+    t.off_j1.clear();
+    t.diag_j0.assign(n_sd, 0);
+    t.diag_j1.assign(n_sd, 0);
+    for (size_t k = 0; k < two.size(); ++k) t.code2[k] = two[k].label * 2 + (two[k].phase < 0 ? 1 : 0);
+    size_t k = 0;
+    while (k < two.size()) {
+        size_t e = k;
+        while (e < two.size() && two[e].dst == two[k].dst && two[e].src == two[k].src) ++e;
+        const int dst = two[k].dst, src = two[k].src;
+        if (src == dst) {
+            t.diag_j0[dst] = (int32_t)k;
+            t.diag_j1[dst] = (int32_t)e;
+        } else {
+            t.off_col.push_back(src);
+            t.off_j0.push_back((int32_t)k);
+            t.off_j1.push_back((int32_t)e);
+            t.off_rowptr[dst + 1]++;
+        }
+        k = e;
+    }
+    for (int i = 0; i < n_sd; ++i) t.off_rowptr[i + 1] += t.off_rowptr[i];
+    // one-body: by (dst, class, src, local op)
+    const OpClasses &cl = j->cls;
+    const int nq = cl.nq;
+    const auto &one = j->rec[sp == 0 ? FOTCI_JUMP_P1 : FOTCI_JUMP_N1];
+    std::vector<JumpRec> ob(one.begin(), one.end());
+    std::stable_sort(ob.begin(), ob.end(), [&](const JumpRec &x, const JumpRec &y) {
+        if (x.dst != y.dst) return x.dst < y.dst;
+        int qx = cl.class_of[x.label], qy = cl.class_of[y.label];
+        if (qx != qy) return qx < qy;
+        if (x.src != y.src) return x.src < y.src;
+        return cl.local_of[x.label] < cl.local_of[y.label];
+    });
+    t.ob_ptr.assign((size_t)n_sd * nq + 1, 0);
+    t.ob_src.resize(ob.size());
+    t.ob_code.resize(ob.size());
+    for (size_t i = 0; i < ob.size(); ++i) {
+        t.ob_ptr[(size_t)ob[i].dst * nq + cl.class_of[ob[i].label] + 1]++;
+        t.ob_src[i] = ob[i].src;
+        t.ob_code[i] = cl.local_of[ob[i].label] * 2 + (ob[i].phase < 0 ? 1 : 0);
+    }
+    for (size_t i = 0; i < (size_t)n_sd * nq; ++i) t.ob_ptr[i + 1] += t.ob_ptr[i];
+}
+
+void block_pn(fotci_ham *h) {
+    const OpClasses &cl = h->j->cls;
+    const int ns = h->j->ns;
+    const size_t ns2 = (size_t)ns * ns;
+    h->vq_off.assign(cl.nq, 0);
+    h->vq_nb.assign(cl.nq, 0);
+    size_t tot = 0;
+    for (int q = 0; q < cl.nq; ++q) {
+        h->vq_off[q] = (int32_t)tot;
+        h->vq_nb[q] = (int32_t)cl.ops[cl.conj[q]].size();
+        tot += cl.ops[q].size() * cl.ops[cl.conj[q]].size();
+    }
+    h->vq.assign(tot, 0.0);
+    for (int q = 0; q < cl.nq; ++q) {
+        const auto &A = cl.ops[q];
+        const auto &B = cl.ops[cl.conj[q]];
+        for (size_t ia = 0; ia < A.size(); ++ia) {
+            const int a = A[ia] / ns, c = A[ia] % ns;
+            for (size_t ib = 0; ib < B.size(); ++ib) {
+                const int bb = B[ib] / ns, d = B[ib] % ns;
+                h->vq[h->vq_off[q] + ia * B.size() + ib] = h->v_pn[((size_t)a * ns + bb) * ns2 + (size_t)c * ns + d];
+            }
+        }
+    }
+}
+
+void fill_species_values(fotci_ham *h) {
+    const fotci_basis *b = h->j->b;
+    for (int sp = 0; sp < 2; ++sp) {
+        HostSpeciesTables &t = sp == 0 ? h->tp : h->tn;
+        const auto &spe = sp == 0 ? h->spe_p : h->spe_n;
+        t.eps.resize(b->ms.size());
+        for (size_t i = 0; i < b->ms.size(); ++i) t.eps[i] = spe[b->ms[i].orbit];
+        t.v2 = sp == 0 ? h->v_pp : h->v_nn;
+    }
+    block_pn(h);
+}
+
+namespace {
+
+void validate(const fotci_jumps *j, const double *spe_p, const double *spe_n, const double *v_pp,
+              const double *v_nn, const double *v_pn) {
+    if (!spe_p || !spe_n || !v_pp || !v_nn || !v_pn) fail(FOTCI_EINVAL, "interaction array is NULL");
+    const auto &ms = j->b->ms;
+    const int ns = j->ns, np = j->npairs;
+    std::vector<int> pa(np), pb(np);
+    for (int a = 0; a < ns; ++a)
+        for (int c = a + 1; c < ns; ++c) {
+            pa[pair_index(a, c, ns)] = a;
+            pb[pair_index(a, c, ns)] = c;
+        }
+    for (int o = 0; o < j->b->n_orbits; ++o)
+        if (!std::isfinite(spe_p[o]) || !std::isfinite(spe_n[o])) fail(FOTCI_EINVAL, "non-finite energy");
+    for (const double *v : {v_pp, v_nn}) {
+        for (int r = 0; r < np; ++r)
+            for (int c = 0; c < np; ++c) {
+                const double x = v[(size_t)r * np + c];
+                if (!std::isfinite(x)) fail(FOTCI_EINVAL, "non-finite two-body matrix element");
+                if (x != v[(size_t)c * np + r]) fail(FOTCI_EINVAL, "two-body matrix not symmetric");
+                const bool ok = ms[pa[r]].two_m + ms[pb[r]].two_m == ms[pa[c]].two_m + ms[pb[c]].two_m &&
+                                ms[pa[r]].parity * ms[pb[r]].parity == ms[pa[c]].parity * ms[pb[c]].parity;
+                if (!ok && x != 0.0) fail(FOTCI_EINVAL, "two-body matrix element violates Jz or parity");
+            }
+    }
+    const size_t n2 = (size_t)ns * ns;
+    for (size_t r = 0; r < n2; ++r)
+        for (size_t c = 0; c < n2; ++c) {
+            const double x = v_pn[r * n2 + c];
+            if (!std::isfinite(x)) fail(FOTCI_EINVAL, "non-finite pn matrix element");
+            if (x != v_pn[c * n2 + r]) fail(FOTCI_EINVAL, "pn matrix not symmetric");
+            const int a = (int)(r / ns), bb = (int)(r % ns), cc = (int)(c / ns), d = (int)(c % ns);
+            const bool ok = ms[a].two_m + ms[bb].two_m == ms[cc].two_m + ms[d].two_m &&
+                            ms[a].parity * ms[bb].parity == ms[cc].parity * ms[d].parity;
+            if (!ok && x != 0.0) fail(FOTCI_EINVAL, "pn matrix element violates Jz or parity");
+        }
+}
+
+void copy_values(fotci_ham *h, const double *spe_p, const double *spe_n, const double *v_pp, const double *v_nn,
+                 const double *v_pn) {
+    const int no = h->j->b->n_orbits, np = h->j->npairs, ns = h->j->ns;
+    h->spe_p.assign(spe_p, spe_p + no);
+    h->spe_n.assign(spe_n, spe_n + no);
+    h->v_pp.assign(v_pp, v_pp + (size_t)np * np);
+    h->v_nn.assign(v_nn, v_nn + (size_t)np * np);
+    h->v_pn.assign(v_pn, v_pn + (size_t)ns * ns * ns * ns);
+}
+
+struct Item {
+    const void *host;
+    size_t bytes;
+    void **dev;
+};
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+// Device-table items in upload order; pointers in h->dev are set from ws.
+std::vector<Item> items(fotci_ham *h) {
+    const fotci_basis *b = h->j->b;
+    DevHam &d = h->dev;
+    std::vector<Item> it;
+    HostCommonTables &c = h->tc;
+    c.p_sector.assign(b->p_basis_sector.begin(), b->p_basis_sector.end());
+    c.n_local.assign(b->n.sd_local.begin(), b->n.sd_local.end());
+    c.sec_nn.clear();
+    c.sec_nfirst.clear();
+    c.sec_pfirst.clear();
+    c.sec_np.clear();
+    c.sec_off.clear();
+    for (const auto &s : b->sectors) {
+        c.sec_nn.push_back(s.nn);
+        c.sec_nfirst.push_back(s.n_first);
+        c.sec_pfirst.push_back(s.p_first);
+        c.sec_np.push_back(s.np);
+        c.sec_off.push_back(s.offset);
+    }
+    c.conjq.assign(h->j->cls.conj.begin(), h->j->cls.conj.end());
+    c.ms_orbit.clear();
+    for (const auto &m : b->ms) c.ms_orbit.push_back(m.orbit);
+    c.n_bsector.assign(b->n.sd.size(), -1);
+    for (size_t s = 0; s < b->sectors.size(); ++s)
+        for (int r = 0; r < b->sectors[s].nn; ++r) c.n_bsector[b->sectors[s].n_first + r] = (int32_t)s;
+    c.cls_off.assign(1, 0);
+    c.cls_ops.clear();
+    for (const auto &ops : h->j->cls.ops) {
+        for (int lab : ops) c.cls_ops.push_back(lab);
+        c.cls_off.push_back((int32_t)c.cls_ops.size());
+    }
+    auto add = [&](const void *p, size_t bytes, void *devfield) { it.push_back({p, bytes, (void **)devfield}); };
+    add(c.p_sector.data(), c.p_sector.size() * 4, &d.p_sector);
+    add(b->pstart.data(), b->pstart.size() * 8, &d.p_pstart);
+    add(c.n_local.data(), c.n_local.size() * 4, &d.n_local);
+    add(c.sec_nn.data(), c.sec_nn.size() * 4, &d.sec_nn);
+    add(c.sec_nfirst.data(), c.sec_nfirst.size() * 4, &d.sec_nfirst);
+    add(c.sec_pfirst.data(), c.sec_pfirst.size() * 4, &d.sec_pfirst);
+    add(c.sec_np.data(), c.sec_np.size() * 4, &d.sec_np);
+    add(c.sec_off.data(), c.sec_off.size() * 8, &d.sec_off);
+    add(c.conjq.data(), c.conjq.size() * 4, &d.conjq);
+    add(c.ms_orbit.data(), c.ms_orbit.size() * 4, &d.ms_orbit);
+    add(c.n_bsector.data(), c.n_bsector.size() * 4, &d.n_bsector);
+    add(c.cls_off.data(), c.cls_off.size() * 4, &d.cls_off);
+    add(c.cls_ops.data(), c.cls_ops.size() * 4, &d.cls_ops);
+    add(h->vq_off.data(), h->vq_off.size() * 4, &d.vq_off);
+    add(h->vq_nb.data(), h->vq_nb.size() * 4, &d.vq_nb);
+    add(h->vq.data(), h->vq.size() * 8, &d.vq64);
+    add(nullptr, h->vq.size() * 4, &d.vq32);
+    add(nullptr, h->tn.masks.size() * 8, &d.scratch_ncol);
+    for (int sp = 0; sp < 2; ++sp) {
+        HostSpeciesTables &t = sp == 0 ? h->tp : h->tn;
+        DevSpecies &ds = sp == 0 ? d.p : d.n;
+        add(t.masks.data(), t.masks.size() * 4, &ds.masks);
+        add(t.code2.data(), t.code2.size() * 4, &ds.code2);
+        add(t.off_rowptr.data(), t.off_rowptr.size() * 4, &ds.off_rowptr);
+        add(t.off_col.data(), t.off_col.size() * 4, &ds.off_col);
+        add(t.off_j0.data(), t.off_j0.size() * 4, &ds.off_j0);
+        add(t.off_j1.data(), t.off_j1.size() * 4, &ds.off_j1);
+        add(t.diag_j0.data(), t.diag_j0.size() * 4, &ds.diag_j0);
+        add(t.diag_j1.data(), t.diag_j1.size() * 4, &ds.diag_j1);
+        add(t.ob_ptr.data(), t.ob_ptr.size() * 4, &ds.ob_ptr);
+        add(t.ob_src.data(), t.ob_src.size() * 4, &ds.ob_src);
+        add(t.ob_code.data(), t.ob_code.size() * 4, &ds.ob_code);
+        add(t.eps.data(), t.eps.size() * 8, &ds.eps);
+        add(t.v2.data(), t.v2.size() * 8, &ds.v2);
+        add(nullptr, t.off_col.size() * 8, &ds.off_val64);
+        add(nullptr, t.off_col.size() * 4, &ds.off_val32);
+        add(nullptr, t.masks.size() * 8, &ds.d64);
+        add(nullptr, t.masks.size() * 4, &ds.d32);
+    }
+    return it;
+}
+
+void fill_dev_scalars(fotci_ham *h) {
+    const fotci_basis *b = h->j->b;
+    DevHam &d = h->dev;
+    d.ns = h->j->ns;
+    d.npairs = h->j->npairs;
+    d.nq = h->j->cls.nq;
+    d.n_sectors = (int32_t)b->sectors.size();
+    d.n_vq = (int32_t)h->vq.size();
+    d.dim = b->dim;
+    d.p.n_sd = (int32_t)h->tp.masks.size();
+    d.p.n_off = (int32_t)h->tp.off_col.size();
+    d.n.n_sd = (int32_t)h->tn.masks.size();
+    d.n.n_off = (int32_t)h->tn.off_col.size();
+}
+
+}  // namespace
+
+}  // namespace fotci
+
+using namespace fotci;
+
+extern "C" int fotci_set_interaction_impl(const fotci_jumps *j, const double *spe_p, const double *spe_n,
+                                          const double *v_pp, const double *v_nn, const double *v_pn,
+                                          fotci_ham **out) {
+    if (!j || !out) fail(FOTCI_EINVAL, "NULL argument");
+    validate(j, spe_p, spe_n, v_pp, v_nn, v_pn);
+    auto *h = new fotci_ham();
+    try {
+        h->j = j;
+        copy_values(h, spe_p, spe_n, v_pp, v_nn, v_pn);
+        build_species_tables(j, 0, h->tp);
+        build_species_tables(j, 1, h->tn);
+        fill_species_values(h);
+        fill_dev_scalars(h);
+        int64_t off = 0;
+        for (auto &x : items(h)) off = align256(off) + (int64_t)x.bytes;
+        h->layout_total = align256(off);
+    } catch (...) {
+        delete h;
+        throw;
+    }
+    *out = h;
+    return FOTCI_OK;
+}
+
+extern "C" int64_t fotci_ham_workspace_bytes_impl(const fotci_ham *h) {
+    if (!h) fail(FOTCI_EINVAL, "NULL handle");
+    return h->layout_total;
+}
+
+extern "C" int fotci_ham_upload_impl(fotci_ham *h, void *ws, int64_t bytes, void *stream) {
+    if (!h || !ws) fail(FOTCI_EINVAL, "NULL argument");
+    if (((uintptr_t)ws & 255u) != 0) fail(FOTCI_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < h->layout_total) fail(FOTCI_ENOMEM, "workspace smaller than fotci_ham_workspace_bytes");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t off = 0;
+    for (auto &x : items(h)) {
+        off = align256(off);
+        *x.dev = (char *)ws + off;
+        if (x.host && x.bytes) hip_check(hipMemcpyAsync(*x.dev, x.host, x.bytes, hipMemcpyHostToDevice, st), "upload");
+        off += (int64_t)x.bytes;
+    }
+    h->ws = ws;
+    h->ws_bytes = bytes;
+    launch_materialize(h->dev, stream);
+    hip_check(hipStreamSynchronize(st), "upload sync");
+    h->uploaded = true;
+    return FOTCI_OK;
+}
+
+extern "C" int fotci_ham_set_values_impl(fotci_ham *h, const double *spe_p, const double *spe_n, const double *v_pp,
+                                         const double *v_nn, const double *v_pn, void *stream) {
+    if (!h) fail(FOTCI_EINVAL, "NULL handle");
+    validate(h->j, spe_p, spe_n, v_pp, v_nn, v_pn);
+    copy_values(h, spe_p, spe_n, v_pp, v_nn, v_pn);
+    fill_species_values(h);
+    if (h->uploaded) {
+        hipStream_t st = (hipStream_t)stream;
+        hip_check(hipMemcpyAsync((void *)h->dev.vq64, h->vq.data(), h->vq.size() * 8, hipMemcpyHostToDevice, st),
+                  "upload");
+        for (int sp = 0; sp < 2; ++sp) {
+            HostSpeciesTables &t = sp == 0 ? h->tp : h->tn;
+            DevSpecies &ds = sp == 0 ? h->dev.p : h->dev.n;
+            hip_check(hipMemcpyAsync((void *)ds.eps, t.eps.data(), t.eps.size() * 8, hipMemcpyHostToDevice, st),
+                      "upload");
+            hip_check(hipMemcpyAsync((void *)ds.v2, t.v2.data(), t.v2.size() * 8, hipMemcpyHostToDevice, st),
+                      "upload");
+        }
+        launch_materialize(h->dev, stream);
+        hip_check(hipStreamSynchronize(st), "upload sync");
+    }
+    return FOTCI_OK;
+}
+
+extern "C" int fotci_ham_op_counts_impl(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn,
+                                        int64_t *ops_diag) {
+    if (!h) fail(FOTCI_EINVAL, "NULL handle");
+    const fotci_basis *b = h->j->b;
+    const int nq = h->j->cls.nq;
+    int64_t pp = 0, nn = 0, pn = 0;
+    for (const auto &s : b->sectors) {
+        for (int ip = s.p_first; ip < s.p_first + s.np; ++ip)
+            pp += (int64_t)(h->tp.off_rowptr[ip + 1] - h->tp.off_rowptr[ip]) * s.nn;
+        for (int jn = s.n_first; jn < s.n_first + s.nn; ++jn)
+            nn += (int64_t)(h->tn.off_rowptr[jn + 1] - h->tn.off_rowptr[jn]) * s.np;
+        for (int q = 0; q < nq; ++q) {
+            const int qn = h->j->cls.conj[q];
+            int64_t cp = 0, cn = 0;
+            for (int ip = s.p_first; ip < s.p_first + s.np; ++ip)
+                cp += h->tp.ob_ptr[(size_t)ip * nq + q + 1] - h->tp.ob_ptr[(size_t)ip * nq + q];
+            for (int jn = s.n_first; jn < s.n_first + s.nn; ++jn)
+                cn += h->tn.ob_ptr[(size_t)jn * nq + qn + 1] - h->tn.ob_ptr[(size_t)jn * nq + qn];
+            pn += cp * cn;
+        }
+    }
+    if (ops_pp) *ops_pp = pp;
+    if (ops_nn) *ops_nn = nn;
+    if (ops_pn) *ops_pn = pn;
+    if (ops_diag) *ops_diag = b->dim;
+    return FOTCI_OK;
+}

@@ -1,0 +1,373 @@
+// Lanczos with full reorthogonalisation on the device (Ch. 7, "Standard
+// Lanczos algorithm"), with float64 reductions for every inner product.
+//
+// Per iteration i: (1) y = H v_i; (2) alpha_i = <v_i, y>; (3)-(4)
+// w = y - alpha_i v_i - beta_{i-1} v_{i-1}; reorthogonalisation against every
+// stored vector by classical Gram-Schmidt, twice (alpha is taken before the
+// reorthogonalisation, the ordering the chapter recommends); (5) beta_i =
+// ||w||; (6) v_{i+1} = w / beta_i. Lanczos vectors are stored in the mode's
+// precision (float64 or float32); w, alpha, beta and the coefficients are
+// float64. The tridiagonal eigenproblem is solved on the host in float64; the
+// Ritz vectors are formed on the device with float64 accumulation and, with
+// refinement, their float64 Rayleigh quotients are the returned eigenvalues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
+#include "fotci_internal.h"
+
+namespace fotci {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kRowsPerThread = 8;
+constexpr int kChunk = kThreads * kRowsPerThread;   // rows per block in the tall-skinny kernels
+constexpr int kMaxIter = 4096;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide float64 sum; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kWaves; ++w) t += lds[w];
+    __syncthreads();
+    return t;
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kThreads) void k_dot_partial(const TA *__restrict__ a, const TB *__restrict__ b,
+                                                          int64_t n, double *__restrict__ partial) {
+    __shared__ double lds[kWaves];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        acc += (double)a[i] * (double)b[i];
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// out[0] = sum(partial[0..nb)) (sqrt if take_sqrt); deterministic order.
+__global__ __launch_bounds__(kThreads) void k_finish(const double *__restrict__ partial, int nb, double *out,
+                                                     int take_sqrt) {
+    __shared__ double lds[kWaves];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) acc += partial[i];
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[0] = take_sqrt ? sqrt(acc) : acc;
+}
+
+// w = y - alpha v_i - beta v_{i-1} (beta term skipped when vprev is null)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_three_term(const T *__restrict__ y, const T *__restrict__ vi,
+                                                         const T *__restrict__ vprev, const double *alpha,
+                                                         const double *beta, double *__restrict__ w, int64_t n) {
+    const double a = *alpha;
+    const double b = vprev ? *beta : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        double t = (double)y[i] - a * (double)vi[i];
+        if (vprev) t -= b * (double)vprev[i];
+        w[i] = t;
+    }
+}
+
+// partial[j*nb + block] = sum over the block's rows of V_j[r] * w[r], j < k.
+// Each thread keeps its rows of w in registers; each wave reduces with
+// shuffles, and the waves' sums meet in LDS once per block.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multidot(const T *__restrict__ V, int64_t ld, int k,
+                                                       const double *__restrict__ w, int64_t n,
+                                                       double *__restrict__ partial) {
+    __shared__ double lds[kWaves][256];
+    const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+    const int nb = gridDim.x;
+    double wr[kRowsPerThread];
+#pragma unroll
+    for (int e = 0; e < kRowsPerThread; ++e) {
+        const int64_t r = r0 + e * kThreads + threadIdx.x;
+        wr[e] = r < n ? w[r] : 0.0;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < k; j0 += 256) {
+        const int jn = min(256, k - j0);
+        for (int jj = 0; jj < jn; ++jj) {
+            const T *vj = V + (int64_t)(j0 + jj) * ld;
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < kRowsPerThread; ++e) {
+                const int64_t r = r0 + e * kThreads + threadIdx.x;
+                if (r < n) acc += (double)vj[r] * wr[e];
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) lds[wid][jj] = acc;
+        }
+        __syncthreads();
+        for (int jj = threadIdx.x; jj < jn; jj += kThreads) {
+            double t = 0.0;
+            for (int q = 0; q < kWaves; ++q) t += lds[q][jj];
+            partial[(int64_t)(j0 + jj) * nb + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// c[j] = sum_b partial[j*nb + b]; one block per j.
+__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double *__restrict__ partial, int nb,
+                                                          double *__restrict__ c) {
+    __shared__ double lds[kWaves];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) acc += partial[(int64_t)j * nb + b];
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) c[j] = acc;
+}
+
+// w[r] -= sum_j c[j] V_j[r]
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_subtract(const T *__restrict__ V, int64_t ld, int k,
+                                                       const double *__restrict__ c, double *__restrict__ w,
+                                                       int64_t n) {
+    __shared__ double cs[kMaxIter];
+    for (int j = threadIdx.x; j < k; j += kThreads) cs[j] = c[j];
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+    double acc[kRowsPerThread];
+#pragma unroll
+    for (int e = 0; e < kRowsPerThread; ++e) acc[e] = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const T *vj = V + (int64_t)j * ld;
+        const double cj = cs[j];
+#pragma unroll
+        for (int e = 0; e < kRowsPerThread; ++e) {
+            const int64_t r = r0 + e * kThreads + threadIdx.x;
+            if (r < n) acc[e] += cj * (double)vj[r];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < kRowsPerThread; ++e) {
+        const int64_t r = r0 + e * kThreads + threadIdx.x;
+        if (r < n) w[r] -= acc[e];
+    }
+}
+
+// out = (T)(in * scale) with scale = 1 / *denom
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale_store(const double *__restrict__ in, const double *denom,
+                                                          T *__restrict__ out, int64_t n) {
+    const double s = 1.0 / *denom;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        out[i] = (T)(in[i] * s);
+}
+
+// Y_j[r] = sum_l V_l[r] S[l*nk + j] for j < nk (float64 accumulation)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ritz(const T *__restrict__ V, int64_t ld, int k,
+                                                   const double *__restrict__ S, int nk, double *__restrict__ Y,
+                                                   int64_t n) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    double acc[16];
+    for (int j = 0; j < nk; ++j) acc[j] = 0.0;
+    for (int l = 0; l < k; ++l) {
+        const double v = (double)V[(int64_t)l * ld + r];
+        for (int j = 0; j < nk; ++j) acc[j] += v * S[l * nk + j];
+    }
+    for (int j = 0; j < nk; ++j) Y[(int64_t)j * n + r] = acc[j];
+}
+
+// r = hy - theta y; partial sums of r^2
+__global__ __launch_bounds__(kThreads) void k_resid_partial(const double *__restrict__ hy,
+                                                            const double *__restrict__ y, const double *theta,
+                                                            int64_t n, double *__restrict__ partial) {
+    __shared__ double lds[kWaves];
+    const double t = *theta;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const double r = hy[i] - t * y[i];
+        acc += r * r;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+int stream_blocks(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
+}
+int chunk_blocks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
+
+int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+struct Layout {
+    int64_t basis, y, w, partial, scal, coef, S, ritz, hy, total;
+};
+
+Layout make_layout(const fotci_ham *h, const fotci_lanczos_opts *o) {
+    const int64_t dim = h->j->b->dim;
+    const int es = (o->mode == FOTCI_MODE_F64 || o->mode == FOTCI_MODE_F64_PLAIN) ? 8 : 4;
+    Layout L{};
+    int64_t off = 0;
+    L.basis = off;
+    off = a256(off + (int64_t)o->n_iter * dim * es);
+    L.y = off;
+    off = a256(off + dim * es);
+    L.w = off;
+    off = a256(off + dim * 8);
+    const int64_t nb = std::max<int64_t>(chunk_blocks(dim), 2048);
+    L.partial = off;
+    off = a256(off + (int64_t)std::max(o->n_iter, 1) * nb * 8);
+    L.scal = off;
+    off = a256(off + 64 * 8);
+    L.coef = off;
+    off = a256(off + (int64_t)o->n_iter * 8);
+    L.S = off;
+    off = a256(off + (int64_t)o->n_iter * o->n_keep * 8);
+    L.ritz = off;
+    off = a256(off + (int64_t)o->n_keep * dim * 8);
+    L.hy = off;
+    off = a256(off + dim * 8);
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, char *work, double *evals,
+         double *resid, double *evecs, double *alpha_out, double *beta_out, hipStream_t st) {
+    const int64_t dim = h->j->b->dim;
+    const Layout L = make_layout(h, o);
+    T *basis = (T *)(work + L.basis);
+    T *y = (T *)(work + L.y);
+    double *w = (double *)(work + L.w);
+    double *partial = (double *)(work + L.partial);
+    double *scal = (double *)(work + L.scal);   // [0]=alpha [1]=beta [2]=norm [3]=theta
+    double *coef = (double *)(work + L.coef);
+    double *Sd = (double *)(work + L.S);
+    double *ritz = evecs ? evecs : (double *)(work + L.ritz);
+    double *hy = (double *)(work + L.hy);
+    const int sb = stream_blocks(dim);
+    const int cb = chunk_blocks(dim);
+    const int mode = o->mode;
+    const int hi_mode = (mode == FOTCI_MODE_F64_PLAIN) ? FOTCI_MODE_F64_PLAIN : FOTCI_MODE_F64;
+
+    auto dot_into = [&](auto *a, auto *b, double *out, int take_sqrt) {
+        hipLaunchKernelGGL((k_dot_partial<std::remove_cv_t<std::remove_pointer_t<decltype(a)>>,
+                                          std::remove_cv_t<std::remove_pointer_t<decltype(b)>>>),
+                           dim3(sb), dim3(kThreads), 0, st, a, b, dim, partial);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, sb, out, take_sqrt);
+    };
+
+    // v_0 = pivot / ||pivot||
+    dot_into(pivot, pivot, scal + 2, 1);
+    hipLaunchKernelGGL(k_scale_store<T>, dim3(sb), dim3(kThreads), 0, st, pivot, (const double *)(scal + 2), basis,
+                       dim);
+    std::vector<double> al, be;
+    double tnorm = 0.0;
+    int k = 0;
+    for (int i = 0; i < o->n_iter; ++i) {
+        T *vi = basis + (int64_t)i * dim;
+        launch_apply(h->dev, mode, vi, y, st);
+        dot_into((const T *)vi, (const T *)y, scal + 0, 0);
+        hipLaunchKernelGGL(k_three_term<T>, dim3(sb), dim3(kThreads), 0, st, (const T *)y, (const T *)vi,
+                           (const T *)(i > 0 ? vi - dim : nullptr), (const double *)(scal + 0),
+                           (const double *)(scal + 1), w, dim);
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_multidot<T>, dim3(cb), dim3(kThreads), 0, st, (const T *)basis, dim, i + 1,
+                               (const double *)w, dim, partial);
+            hipLaunchKernelGGL(k_reduce_rows, dim3(i + 1), dim3(kThreads), 0, st, (const double *)partial, cb, coef);
+            hipLaunchKernelGGL(k_subtract<T>, dim3(cb), dim3(kThreads), 0, st, (const T *)basis, dim, i + 1,
+                               (const double *)coef, w, dim);
+        }
+        dot_into((const double *)w, (const double *)w, scal + 1, 1);
+        hip_check(hipGetLastError(), "lanczos launch");
+        double ab[2];
+        hip_check(hipMemcpyAsync(ab, scal, 16, hipMemcpyDeviceToHost, st), "lanczos copy");
+        hip_check(hipStreamSynchronize(st), "lanczos sync");
+        al.push_back(ab[0]);
+        k = i + 1;
+        tnorm = std::max(tnorm, std::fabs(ab[0]) + ab[1] + (be.empty() ? 0.0 : be.back()));
+        if (i == o->n_iter - 1) {
+            be.push_back(ab[1]);
+            break;
+        }
+        be.push_back(ab[1]);
+        if (!(ab[1] > 1e-12 * tnorm)) break;   // invariant subspace reached
+        hipLaunchKernelGGL(k_scale_store<T>, dim3(sb), dim3(kThreads), 0, st, (const double *)w,
+                           (const double *)(scal + 1), basis + (int64_t)(i + 1) * dim, dim);
+    }
+    if (alpha_out)
+        for (int i = 0; i < o->n_iter; ++i) alpha_out[i] = i < k ? al[i] : 0.0;
+    if (beta_out)
+        for (int i = 0; i < o->n_iter; ++i) beta_out[i] = i < (int)be.size() ? be[i] : 0.0;
+    if (k < o->n_keep) fail(FOTCI_ENOTCONV, "Krylov space smaller than n_keep");
+    // tridiagonal eigenproblem
+    std::vector<double> d(al.begin(), al.begin() + k), e(k > 1 ? k - 1 : 0), z;
+    for (int i = 0; i + 1 < k; ++i) e[i] = be[i];
+    tridiag_eig(k, d, e, z);
+    const int nk = o->n_keep;
+    std::vector<double> S((size_t)k * nk);
+    for (int l = 0; l < k; ++l)
+        for (int j = 0; j < nk; ++j) S[(size_t)l * nk + j] = z[(size_t)l * k + j];
+    hip_check(hipMemcpyAsync(Sd, S.data(), S.size() * 8, hipMemcpyHostToDevice, st), "ritz copy");
+    hipLaunchKernelGGL(k_ritz<T>, dim3((int)((dim + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                       (const T *)basis, dim, k, (const double *)Sd, nk, ritz, dim);
+    for (int j = 0; j < nk; ++j) {
+        double *yj = ritz + (int64_t)j * dim;
+        // normalise the Ritz vector in float64
+        dot_into((const double *)yj, (const double *)yj, scal + 2, 1);
+        hipLaunchKernelGGL(k_scale_store<double>, dim3(sb), dim3(kThreads), 0, st, (const double *)yj,
+                           (const double *)(scal + 2), yj, dim);
+        launch_apply(h->dev, hi_mode, yj, hy, st);
+        if (o->refine) {
+            dot_into((const double *)yj, (const double *)hy, scal + 3, 0);
+        } else {
+            hip_check(hipMemcpyAsync(scal + 3, &d[j], 8, hipMemcpyHostToDevice, st), "theta copy");
+        }
+        hipLaunchKernelGGL(k_resid_partial, dim3(sb), dim3(kThreads), 0, st, (const double *)hy, (const double *)yj,
+                           (const double *)(scal + 3), dim, partial);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, sb, scal + 4, 1);
+        double tr[2];
+        hip_check(hipMemcpyAsync(tr, scal + 3, 16, hipMemcpyDeviceToHost, st), "ritz copy");
+        hip_check(hipStreamSynchronize(st), "ritz sync");
+        evals[j] = tr[0];
+        resid[j] = tr[1];
+    }
+    hip_check(hipGetLastError(), "ritz launch");
+}
+
+}  // namespace
+
+int64_t lanczos_bytes(const fotci_ham *h, const fotci_lanczos_opts *o) { return make_layout(h, o).total; }
+
+void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, void *work, int64_t work_bytes,
+                 double *evals, double *resid, double *evecs, double *alpha, double *beta, void *stream) {
+    if (o->n_keep < 1 || o->n_keep > 16) fail(FOTCI_EINVAL, "n_keep must be in 1..16");
+    if (o->n_iter < o->n_keep || o->n_iter > kMaxIter) fail(FOTCI_EINVAL, "n_iter must be in n_keep..4096");
+    if (work_bytes < lanczos_bytes(h, o)) fail(FOTCI_ENOMEM, "Lanczos workspace too small");
+    if (((uintptr_t)work & 255u) != 0) fail(FOTCI_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    switch (o->mode) {
+        case FOTCI_MODE_F64_PLAIN:
+        case FOTCI_MODE_F64:
+            run<double>(h, o, pivot, (char *)work, evals, resid, evecs, alpha, beta, st);
+            break;
+        case FOTCI_MODE_F32:
+        case FOTCI_MODE_BF16X3:
+            run<float>(h, o, pivot, (char *)work, evals, resid, evecs, alpha, beta, st);
+            break;
+        default:
+            fail(FOTCI_EINVAL, "unknown mode");
+    }
+}
+
+}  // namespace fotci

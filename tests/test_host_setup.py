@@ -1,0 +1,164 @@
+"""CPU tests of the library's host side against the oracle (no GPU needed).
+
+Basis tables and jump lists must match the oracle bit-exactly; bad inputs
+must be rejected with FOTCI_EINVAL; every symbol the header declares must be
+exported.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis as ob
+from oracle import hamiltonian as oh
+from paper_1801_08432_amd import fotci, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "fotci.h")).read()
+    names = set(re.findall(r"\b(fotci_[a-zA-Z0-9_]+)\s*\(", hdr))
+    names.discard("fotci_lanczos_opts")
+    lib = fotci.lib()
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert names == set(fotci.EXPORTED)
+
+
+@pytest.mark.parametrize("name", list(inputs.WORKLOADS))
+def test_basis_matches_oracle(name):
+    w = inputs.WORKLOADS[name]
+    b = fotci.Basis(w["two_j"], w["Z"], w["N"], w["two_M"], w["parity"])
+    o = ob.build_basis(w["two_j"], w["Z"], w["N"], w["two_M"], w["parity"])
+    e = b.export()
+    assert b.dim == o.dim
+    assert np.array_equal(e["p_bits"], np.array(o.p_sds, dtype=np.uint32))
+    assert np.array_equal(e["n_bits"], np.array(o.n_sds, dtype=np.uint32))
+    assert np.array_equal(e["pstart"], np.array(o.pstart, dtype=np.int64))
+    assert np.array_equal(e["nstart"], np.array(o.nstart, dtype=np.int64))
+    assert np.array_equal(e["sectors"], np.array(ob.sector_table(o), dtype=np.int64))
+
+
+@pytest.mark.parametrize("space,Z,N,two_M,par", [((5, 1, 3), 5, 6, 1, 1), ((1, 3), 2, 2, 0, 1)])
+def test_basis_printed_cases(space, Z, N, two_M, par):
+    o = ob.build_basis(space, Z, N, two_M, par)
+    b = fotci.Basis(space, Z, N, two_M, par)
+    assert b.dim == o.dim and b.n_psd == len(o.p_sds) and b.n_nsd == len(o.n_sds)
+
+
+def test_basis_with_mixed_parity_orbits():
+    space, opar = (1, 3, 5, 1), (1, 1, -1, -1)
+    for tot in (1, -1):
+        o = ob.build_basis(space, 3, 2, 1, tot, orbit_parity=opar)
+        b = fotci.Basis(space, 3, 2, 1, tot, orbit_parity=opar)
+        e = b.export()
+        assert np.array_equal(e["sectors"], np.array(ob.sector_table(o), dtype=np.int64))
+        assert np.array_equal(e["p_bits"], np.array(o.p_sds, dtype=np.uint32))
+
+
+def _compare_jumps(b, o, species, kinds, src_subset=None):
+    j = fotci.Jumps(b)
+    ref = oh.jumps(o, species, src_subset)
+    for kind, key in kinds:
+        got = j.export(kind)
+        if src_subset is not None:
+            got = got[np.isin(got[:, 0], np.array(sorted(src_subset)))]
+        assert got.shape == ref[key].shape, (species, key)
+        assert np.array_equal(got, ref[key]), (species, key)
+    return j
+
+
+@pytest.mark.parametrize("name", ["sd_2p2n", "sd_6p6n"])
+def test_jumps_match_oracle_exactly(name):
+    w = inputs.WORKLOADS[name]
+    b = fotci.Basis(w["two_j"], w["Z"], w["N"], w["two_M"])
+    o = ob.build_basis(w["two_j"], w["Z"], w["N"], w["two_M"])
+    _compare_jumps(b, o, "p", [(fotci.JUMP_PP2, "two_body"), (fotci.JUMP_P1, "one_body")])
+    _compare_jumps(b, o, "n", [(fotci.JUMP_NN2, "two_body"), (fotci.JUMP_N1, "one_body")])
+
+
+def test_jumps_mixed_parity_and_unequal_species():
+    space, opar = (1, 3, 5, 1), (1, 1, -1, -1)
+    b = fotci.Basis(space, 3, 2, 1, -1, orbit_parity=opar)
+    o = ob.build_basis(space, 3, 2, 1, -1, orbit_parity=opar)
+    _compare_jumps(b, o, "p", [(fotci.JUMP_PP2, "two_body"), (fotci.JUMP_P1, "one_body")])
+    _compare_jumps(b, o, "n", [(fotci.JUMP_NN2, "two_body"), (fotci.JUMP_N1, "one_body")])
+
+
+@pytest.mark.parametrize("name", ["pf_4p4n", "pf_5p5n"])
+def test_jumps_match_oracle_sampled(name):
+    w = inputs.WORKLOADS[name]
+    b = fotci.Basis(w["two_j"], w["Z"], w["N"], w["two_M"])
+    o = ob.build_basis(w["two_j"], w["Z"], w["N"], w["two_M"])
+    rng = np.random.default_rng(5)
+    sub = set(rng.choice(len(o.p_sds), 60, replace=False).tolist()) | {0, len(o.p_sds) - 1}
+    j = _compare_jumps(b, o, "p", [(fotci.JUMP_PP2, "two_body"), (fotci.JUMP_P1, "one_body")], sub)
+    # closed-form count: every SD has n (N_s - n + 1) one-body jumps when all sectors are kept
+    assert j.count(fotci.JUMP_P1) == len(o.p_sds) * w["Z"] * (20 - w["Z"] + 1)
+
+
+@pytest.mark.parametrize("args", [
+    dict(two_j=(1, 3, 5), Z=2, N=2, two_M=1),         # 2M parity vs Z+N
+    dict(two_j=(1, 3, 5), Z=13, N=2, two_M=1),        # Z > N_s
+    dict(two_j=(1, 3, 5), Z=2, N=2, two_M=40),        # empty basis
+    dict(two_j=(2, 3), Z=1, N=1, two_M=0),            # even 2j
+    dict(two_j=(31, 3), Z=1, N=1, two_M=0),           # more than 32 m-states
+])
+def test_bad_basis_arguments_are_rejected(args):
+    with pytest.raises(fotci.FotciError) as e:
+        fotci.Basis(args["two_j"], args["Z"], args["N"], args["two_M"])
+    assert e.value.code == -1
+
+
+def test_bad_interactions_are_rejected():
+    w = inputs.workload("sd_2p2n")
+    b = fotci.Basis(w["two_j"], 2, 2, 0)
+    j = fotci.Jumps(b)
+    fotci.Hamiltonian(j, w)        # the good one is accepted
+    bad = dict(w)
+    bad["v_pp"] = w["v_pp"].copy()
+    bad["v_pp"][0, 1] += 1e-3      # not symmetric
+    with pytest.raises(fotci.FotciError):
+        fotci.Hamiltonian(j, bad)
+    bad = dict(w)
+    bad["v_pn"] = w["v_pn"].copy()
+    # (a=0,b=0) -> (c=0,d=1) changes 2M: must be zero
+    bad["v_pn"][0, 1] = bad["v_pn"][1, 0] = 0.5
+    with pytest.raises(fotci.FotciError):
+        fotci.Hamiltonian(j, bad)
+    bad = dict(w)
+    bad["eps_p"] = np.array([np.nan, 0, 0])
+    with pytest.raises(fotci.FotciError):
+        fotci.Hamiltonian(j, bad)
+
+
+def test_tridiagonal_solver_matches_numpy():
+    rng = np.random.default_rng(2)
+    for n in (1, 2, 3, 17, 120):
+        d = rng.standard_normal(n)
+        e = rng.standard_normal(max(n - 1, 0))
+        T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+        ev, vec = fotci.tridiag_eigh(d, e)
+        ref = np.linalg.eigvalsh(T)
+        assert np.allclose(ev, ref, atol=1e-12 * max(1, np.abs(ref).max()))
+        assert np.allclose(T @ vec, vec * ev, atol=1e-10)
+        assert np.allclose(vec.T @ vec, np.eye(n), atol=1e-12)
+    # degenerate and split cases
+    d = np.array([1.0, 1.0, 1.0, 2.0])
+    e = np.array([0.0, 0.0, 1e-300])
+    ev, vec = fotci.tridiag_eigh(d, e)
+    assert np.allclose(ev, [1, 1, 1, 2])
+
+
+def test_op_counts_pin():
+    """Operation counts per apply_H against Table timetable (Ch. 3): 48Cr in the
+    pf shell "1.5 B" ops and 24Mg in the sd shell "8.6 M" (the paper notes an
+    operation is only approximately a matrix element)."""
+    for (space, Z, N, printed) in [(inputs.PF_SHELL_LIKE, 4, 4, 1.5e9), (inputs.SD_SHELL_LIKE, 4, 4, 8.6e6)]:
+        inter, _ = inputs.random_interaction(space, 1)
+        h = fotci.Hamiltonian.build(space, Z, N, 0, inter, upload=False)
+        c = h.op_counts()
+        tot = c["pp"] + c["nn"] + c["pn"] + c["diag"]
+        assert 0.85 * printed < tot < 1.15 * printed, (c, tot)
