@@ -166,7 +166,7 @@ int fotci_apply_H(const fotci_ham *h, int32_t mode, const void *x, void *y, void
         if (!h || !x || !y) fail(FOTCI_EINVAL, "NULL argument");
         if (!h->uploaded) fail(FOTCI_ESTATE, "Hamiltonian not uploaded");
         if (x == y) fail(FOTCI_EINVAL, "x and y must not overlap");
-        launch_apply(h->dev, mode, x, y, stream);
+        launch_apply(h, mode, x, y, stream);
         return FOTCI_OK;
     });
 }

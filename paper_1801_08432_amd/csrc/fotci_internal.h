@@ -134,6 +134,22 @@ struct DevHam {
     DevSpecies p, n;
 };
 
+// Extra device tables of the tiled kernels.
+struct DevTiled {
+    const int32_t *order;        // [n_psd] workgroup -> destination proton SD (largest rows first)
+    const int64_t *p_off_base;   // [p.n_off] pstart of the source SD of each proton two-body entry
+    const int64_t *p_ob_base;    // [proton one-body jumps] pstart of the source SD
+    const int32_t *n_off_local;  // [n.n_off] local index of the source neutron SD
+    const int32_t *n_ob_code;    // [neutron one-body jumps] (local src << 11) | (B << 1) | (phase < 0)
+    int32_t ok;                  // every class has <= 64 ops and sectors have < 2^20 neutron SDs
+};
+
+struct HostTiled {
+    std::vector<int32_t> order, n_off_local, n_ob_code;
+    std::vector<int64_t> p_off_base, p_ob_base;
+    bool ok = false;
+};
+
 // Host-side tables (built once per jumps + interaction layout).
 struct HostCommonTables {
     std::vector<int32_t> p_sector, n_local, sec_nn, sec_nfirst, sec_pfirst, sec_np, conjq;
@@ -157,6 +173,8 @@ struct fotci_ham {
     std::vector<int32_t> vq_off, vq_nb;
     fotci::HostSpeciesTables tp, tn;
     fotci::HostCommonTables tc;
+    fotci::HostTiled tt;
+    fotci::DevTiled dev_tiled{};
     // device
     bool uploaded = false;
     void *ws = nullptr;
@@ -176,7 +194,10 @@ void fill_species_values(fotci_ham *h);
 
 // device helpers (kernels_*.hip)
 void launch_materialize(const DevHam &d, void *stream);
-void launch_apply(const DevHam &d, int mode, const void *x, void *y, void *stream);
+void launch_apply(const fotci_ham *h, int mode, const void *x, void *y, void *stream);
+void launch_apply_plain(const DevHam &d, int mode, const void *x, void *y, void *stream);
+void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream);
+void build_tiled_tables(fotci_ham *h);
 void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g,
                 double *dx, double *d_spe_p, double *d_spe_n, double *d_v_pp, double *d_v_nn,
                 double *d_v_pn, void *stream);
@@ -189,7 +210,6 @@ void hip_check(int err, const char *what);
 // tridiagonal symmetric eigenproblem (host, float64): implicit QL with
 // Wilkinson shifts; eigenvalues ascending in d, eigenvectors in z (n x n,
 // column k = eigenvector k, row-major storage z[i*n+k]).
-void launch_apply_any(const fotci_ham *h, int mode, const void *x, void *y, void *stream);
 void tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, std::vector<double> &z);
 
 }  // namespace fotci

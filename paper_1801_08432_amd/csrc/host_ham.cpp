@@ -76,6 +76,39 @@ void build_species_tables(const fotci_jumps *j, int sp, HostSpeciesTables &t) {
     for (size_t i = 0; i < (size_t)n_sd * nq; ++i) t.ob_ptr[i + 1] += t.ob_ptr[i];
 }
 
+// Extra tables of the tiled kernels: precomputed source offsets, packed
+// neutron one-body codes, and the workgroup order (rows of the largest
+// sectors first, so the longest workgroups start early).
+void build_tiled_tables(fotci_ham *h) {
+    const fotci_basis *b = h->j->b;
+    const OpClasses &cl = h->j->cls;
+    HostTiled &t = h->tt;
+    bool ok = true;
+    for (int q = 0; q < cl.nq; ++q)
+        if (cl.ops[q].size() > 64) ok = false;
+    for (const auto &s : b->sectors)
+        if (s.nn >= (1 << 20)) ok = false;
+    t.ok = ok;
+    t.p_off_base.resize(h->tp.off_col.size());
+    for (size_t k = 0; k < h->tp.off_col.size(); ++k) t.p_off_base[k] = b->pstart[h->tp.off_col[k]];
+    t.p_ob_base.resize(h->tp.ob_src.size());
+    for (size_t k = 0; k < h->tp.ob_src.size(); ++k) t.p_ob_base[k] = b->pstart[h->tp.ob_src[k]];
+    t.n_off_local.resize(h->tn.off_col.size());
+    for (size_t k = 0; k < h->tn.off_col.size(); ++k) t.n_off_local[k] = b->n.sd_local[h->tn.off_col[k]];
+    t.n_ob_code.resize(h->tn.ob_src.size());
+    for (size_t k = 0; k < h->tn.ob_src.size(); ++k) {
+        const int32_t loc = ok ? b->n.sd_local[h->tn.ob_src[k]] : 0;
+        const int32_t B = h->tn.ob_code[k] >> 1;
+        t.n_ob_code[k] = (loc << 11) | ((B & 1023) << 1) | (h->tn.ob_code[k] & 1);
+    }
+    const int npsd = (int)b->p.sd.size();
+    t.order.resize(npsd);
+    for (int i = 0; i < npsd; ++i) t.order[i] = i;
+    std::stable_sort(t.order.begin(), t.order.end(), [&](int x, int y) {
+        return b->sectors[b->p_basis_sector[x]].nn > b->sectors[b->p_basis_sector[y]].nn;
+    });
+}
+
 void block_pn(fotci_ham *h) {
     const OpClasses &cl = h->j->cls;
     const int ns = h->j->ns;
@@ -222,6 +255,14 @@ std::vector<Item> items(fotci_ham *h) {
     add(h->vq.data(), h->vq.size() * 8, &d.vq64);
     add(nullptr, h->vq.size() * 4, &d.vq32);
     add(nullptr, h->tn.masks.size() * 8, &d.scratch_ncol);
+    HostTiled &tt = h->tt;
+    DevTiled &dt = h->dev_tiled;
+    dt.ok = tt.ok ? 1 : 0;
+    add(tt.order.data(), tt.order.size() * 4, &dt.order);
+    add(tt.p_off_base.data(), tt.p_off_base.size() * 8, &dt.p_off_base);
+    add(tt.p_ob_base.data(), tt.p_ob_base.size() * 8, &dt.p_ob_base);
+    add(tt.n_off_local.data(), tt.n_off_local.size() * 4, &dt.n_off_local);
+    add(tt.n_ob_code.data(), tt.n_ob_code.size() * 4, &dt.n_ob_code);
     for (int sp = 0; sp < 2; ++sp) {
         HostSpeciesTables &t = sp == 0 ? h->tp : h->tn;
         DevSpecies &ds = sp == 0 ? d.p : d.n;
@@ -278,6 +319,7 @@ extern "C" int fotci_set_interaction_impl(const fotci_jumps *j, const double *sp
         copy_values(h, spe_p, spe_n, v_pp, v_nn, v_pn);
         build_species_tables(j, 0, h->tp);
         build_species_tables(j, 1, h->tn);
+        build_tiled_tables(h);
         fill_species_values(h);
         fill_dev_scalars(h);
         int64_t off = 0;

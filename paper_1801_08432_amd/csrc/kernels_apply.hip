@@ -141,23 +141,31 @@ void launch_materialize(const DevHam &d, void *stream) {
     hip_check(hipGetLastError(), "materialize launch");
 }
 
-void launch_apply(const DevHam &d, int mode, const void *x, void *y, void *stream) {
+// The plain kernel in float64 (FOTCI_MODE_F64_PLAIN) or float32 (used for
+// reference timings only).
+void launch_apply_plain(const DevHam &d, int mode, const void *x, void *y, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int grid = d.p.n_sd;
     if (grid == 0) return;
+    if (mode == FOTCI_MODE_F64_PLAIN)
+        hipLaunchKernelGGL(k_apply_plain<double>, dim3(grid), dim3(256), 0, st, d, (const double *)x, (double *)y);
+    else
+        hipLaunchKernelGGL(k_apply_plain<float>, dim3(grid), dim3(256), 0, st, d, (const float *)x, (float *)y);
+    hip_check(hipGetLastError(), "apply launch");
+}
+
+void launch_apply(const fotci_ham *h, int mode, const void *x, void *y, void *stream) {
     switch (mode) {
         case FOTCI_MODE_F64_PLAIN:
-        case FOTCI_MODE_F64:
-            hipLaunchKernelGGL(k_apply_plain<double>, dim3(grid), dim3(256), 0, st, d, (const double *)x, (double *)y);
+            launch_apply_plain(h->dev, mode, x, y, stream);
             break;
+        case FOTCI_MODE_F64:
         case FOTCI_MODE_F32:
-        case FOTCI_MODE_BF16X3:
-            hipLaunchKernelGGL(k_apply_plain<float>, dim3(grid), dim3(256), 0, st, d, (const float *)x, (float *)y);
+            launch_apply_tiled(h->dev, h->dev_tiled, mode, x, y, stream);
             break;
         default:
-            fail(FOTCI_EINVAL, "unknown mode");
+            fail(FOTCI_EINVAL, "unknown or unsupported mode");
     }
-    hip_check(hipGetLastError(), "apply launch");
 }
 
 }  // namespace fotci

@@ -276,7 +276,7 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
     int k = 0;
     for (int i = 0; i < o->n_iter; ++i) {
         T *vi = basis + (int64_t)i * dim;
-        launch_apply(h->dev, mode, vi, y, st);
+        launch_apply(h, mode, vi, y, st);
         dot_into((const T *)vi, (const T *)y, scal + 0, 0);
         hipLaunchKernelGGL(k_three_term<T>, dim3(sb), dim3(kThreads), 0, st, (const T *)y, (const T *)vi,
                            (const T *)(i > 0 ? vi - dim : nullptr), (const double *)(scal + 0),
@@ -327,7 +327,7 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
         dot_into((const double *)yj, (const double *)yj, scal + 2, 1);
         hipLaunchKernelGGL(k_scale_store<double>, dim3(sb), dim3(kThreads), 0, st, (const double *)yj,
                            (const double *)(scal + 2), yj, dim);
-        launch_apply(h->dev, hi_mode, yj, hy, st);
+        launch_apply(h, hi_mode, yj, hy, st);
         if (o->refine) {
             dot_into((const double *)yj, (const double *)hy, scal + 3, 0);
         } else {

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kT) void k_vjp_pn(DevHam P, const double *__restric
 void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g, double *dx, double *d_spe_p,
                 double *d_spe_n, double *d_v_pp, double *d_v_nn, double *d_v_pn, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (dx) launch_apply(d, FOTCI_MODE_F64, g, dx, stream);
+    if (dx) launch_apply(h, FOTCI_MODE_F64, g, dx, stream);
     double *dcol = nullptr;
     const bool need_n = d_spe_n || d_v_nn;
     if (need_n) {
