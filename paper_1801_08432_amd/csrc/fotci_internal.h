@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fotci.h"
+#include "fotci.h"
 
 namespace fotci {
 
@@ -134,19 +134,45 @@ struct DevHam {
     DevSpecies p, n;
 };
 
-// Extra device tables of the tiled kernels.
+// Extra device tables of the tiled kernels (indexed by basis sector s; each
+// basis sector owns one proton and one neutron species sector).
 struct DevTiled {
-    const int32_t *order;        // [n_psd] workgroup -> destination proton SD (largest rows first)
-    const int64_t *p_off_base;   // [p.n_off] pstart of the source SD of each proton two-body entry
+    const int32_t *order;        // [n_psd] pn workgroup -> destination proton SD (largest rows first)
     const int64_t *p_ob_base;    // [proton one-body jumps] pstart of the source SD
-    const int32_t *n_off_local;  // [n.n_off] local index of the source neutron SD
-    const int32_t *n_ob_code;    // [neutron one-body jumps] (local src << 11) | (B << 1) | (phase < 0)
-    int32_t ok;                  // every class has <= 64 ops and sectors have < 2^20 neutron SDs
+    // nn: per sector an ELL table over destination neutron columns, entry e of
+    // column c at ell_base[s] + e*nn_s + c (padding: src 0, value 0)
+    const int64_t *nn_ell_base;  // [n_sectors]
+    const int32_t *nn_ell_E;     // [n_sectors]
+    const int32_t *nn_ell_src;   // local source column
+    const int32_t *nn_ell_ent;   // merged neutron entry index, -1 for padding
+    double *nn_ell_v64;
+    float *nn_ell_v32;
+    // pp: per sector an ELL table over destination proton rows (e*np_s + r)
+    const int64_t *pp_ell_base;
+    const int32_t *pp_ell_E;
+    const int32_t *pp_ell_src;   // local source row
+    const int32_t *pp_ell_ent;
+    double *pp_ell_v64;
+    float *pp_ell_v32;
+    int64_t nn_ell_len, pp_ell_len;
+    // nn / pp workgroup tiles
+    const int32_t *rt_sec, *rt_r0;   // [n_rtiles] row tiles (nn kernel)
+    const int32_t *ct_sec, *ct_c0;   // [n_ctiles] column tiles (pp kernel)
+    int32_t n_rtiles, n_ctiles, rt_rows, ct_cols;
+    // pn neutron gather lists grouped by (destination sector, neutron class, source chunk)
+    const int32_t *pn_ptr;       // [(n_sectors*nq)*n_chunk + 1]
+    const uint32_t *pn_code;     // (dst col << 14) | (src col - chunk start) << 7 | B << 1 | (phase < 0)
+    int32_t n_chunk;             // chunks per sector slot (ceil(max nn / 128))
+    int32_t max_nn, max_np;
+    int32_t ok;
 };
 
 struct HostTiled {
-    std::vector<int32_t> order, n_off_local, n_ob_code;
-    std::vector<int64_t> p_off_base, p_ob_base;
+    std::vector<int32_t> order, nn_ell_E, nn_ell_src, nn_ell_ent, pp_ell_E, pp_ell_src, pp_ell_ent;
+    std::vector<int64_t> p_ob_base, nn_ell_base, pp_ell_base;
+    std::vector<int32_t> rt_sec, rt_r0, ct_sec, ct_c0, pn_ptr;
+    std::vector<uint32_t> pn_code;
+    int n_chunk = 0, max_nn = 0, max_np = 0;
     bool ok = false;
 };
 
@@ -193,7 +219,8 @@ void block_pn(fotci_ham *h);
 void fill_species_values(fotci_ham *h);
 
 // device helpers (kernels_*.hip)
-void launch_materialize(const DevHam &d, void *stream);
+void launch_materialize(const fotci_ham *h, void *stream);
+void launch_materialize_tiled(const DevHam &d, const DevTiled &t, void *stream);
 void launch_apply(const fotci_ham *h, int mode, const void *x, void *y, void *stream);
 void launch_apply_plain(const DevHam &d, int mode, const void *x, void *y, void *stream);
 void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream);

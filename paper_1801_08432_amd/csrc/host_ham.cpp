@@ -76,31 +76,99 @@ void build_species_tables(const fotci_jumps *j, int sp, HostSpeciesTables &t) {
     for (size_t i = 0; i < (size_t)n_sd * nq; ++i) t.ob_ptr[i + 1] += t.ob_ptr[i];
 }
 
-// Extra tables of the tiled kernels: precomputed source offsets, packed
-// neutron one-body codes, and the workgroup order (rows of the largest
-// sectors first, so the longest workgroups start early).
+// Extra tables of the tiled kernels: ELL layouts of the merged pp and nn
+// entries per sector, the workgroup tiles, the neutron one-body jumps
+// regrouped by source chunk for the pn gather, and the pn workgroup order
+// (rows of the largest sectors first, so the longest workgroups start early).
 void build_tiled_tables(fotci_ham *h) {
     const fotci_basis *b = h->j->b;
     const OpClasses &cl = h->j->cls;
+    const int nq = cl.nq;
+    const int S = (int)b->sectors.size();
     HostTiled &t = h->tt;
+    constexpr int kCH = 128;   // source chunk of the pn kernel
     bool ok = true;
-    for (int q = 0; q < cl.nq; ++q)
+    for (int q = 0; q < nq; ++q)
         if (cl.ops[q].size() > 64) ok = false;
-    for (const auto &s : b->sectors)
-        if (s.nn >= (1 << 20)) ok = false;
+    t.max_nn = t.max_np = 0;
+    for (const auto &s : b->sectors) {
+        t.max_nn = std::max(t.max_nn, s.nn);
+        t.max_np = std::max(t.max_np, s.np);
+    }
+    // LDS tiles hold up to 64 KiB of float64 (8 rows / columns of the largest sector)
+    if ((int64_t)t.max_nn * 8 > 65536 || (int64_t)t.max_np * 8 > 65536 || t.max_nn >= (1 << 18)) ok = false;
     t.ok = ok;
-    t.p_off_base.resize(h->tp.off_col.size());
-    for (size_t k = 0; k < h->tp.off_col.size(); ++k) t.p_off_base[k] = b->pstart[h->tp.off_col[k]];
     t.p_ob_base.resize(h->tp.ob_src.size());
     for (size_t k = 0; k < h->tp.ob_src.size(); ++k) t.p_ob_base[k] = b->pstart[h->tp.ob_src[k]];
-    t.n_off_local.resize(h->tn.off_col.size());
-    for (size_t k = 0; k < h->tn.off_col.size(); ++k) t.n_off_local[k] = b->n.sd_local[h->tn.off_col[k]];
-    t.n_ob_code.resize(h->tn.ob_src.size());
-    for (size_t k = 0; k < h->tn.ob_src.size(); ++k) {
-        const int32_t loc = ok ? b->n.sd_local[h->tn.ob_src[k]] : 0;
-        const int32_t B = h->tn.ob_code[k] >> 1;
-        t.n_ob_code[k] = (loc << 11) | ((B & 1023) << 1) | (h->tn.ob_code[k] & 1);
+    // ELL tables
+    auto ell = [&](const HostSpeciesTables &ts, const SpeciesBasis &sb, bool neutron, std::vector<int64_t> &base,
+                   std::vector<int32_t> &E, std::vector<int32_t> &src, std::vector<int32_t> &ent) {
+        base.assign(S, 0);
+        E.assign(S, 0);
+        src.clear();
+        ent.clear();
+        for (int s = 0; s < S; ++s) {
+            const auto &bs = b->sectors[s];
+            const int first = neutron ? bs.n_first : bs.p_first;
+            const int n = neutron ? bs.nn : bs.np;
+            int e = 0;
+            for (int i = 0; i < n; ++i) e = std::max(e, ts.off_rowptr[first + i + 1] - ts.off_rowptr[first + i]);
+            E[s] = e;
+            base[s] = (int64_t)src.size();
+            src.resize(src.size() + (size_t)e * n, 0);
+            ent.resize(ent.size() + (size_t)e * n, -1);
+            for (int i = 0; i < n; ++i)
+                for (int k = ts.off_rowptr[first + i], r = 0; k < ts.off_rowptr[first + i + 1]; ++k, ++r) {
+                    src[base[s] + (int64_t)r * n + i] = sb.sd_local[ts.off_col[k]];
+                    ent[base[s] + (int64_t)r * n + i] = k;
+                }
+        }
+    };
+    ell(h->tn, b->n, true, t.nn_ell_base, t.nn_ell_E, t.nn_ell_src, t.nn_ell_ent);
+    ell(h->tp, b->p, false, t.pp_ell_base, t.pp_ell_E, t.pp_ell_src, t.pp_ell_ent);
+    // workgroup tiles: 8 rows (nn kernel) / 8 columns (pp kernel) per tile
+    t.rt_sec.clear();
+    t.rt_r0.clear();
+    t.ct_sec.clear();
+    t.ct_c0.clear();
+    for (int s = 0; s < S; ++s) {
+        for (int r = 0; r < b->sectors[s].np; r += 8) {
+            t.rt_sec.push_back(s);
+            t.rt_r0.push_back(r);
+        }
+        for (int c = 0; c < b->sectors[s].nn; c += 8) {
+            t.ct_sec.push_back(s);
+            t.ct_c0.push_back(c);
+        }
     }
+    // pn gather lists: neutron one-body jumps into the columns of each
+    // destination sector, grouped by (neutron class, source chunk)
+    t.n_chunk = (t.max_nn + kCH - 1) / kCH;
+    const int nch = std::max(t.n_chunk, 1);
+    std::vector<int64_t> cnt((size_t)S * nq * nch + 1, 0);
+    std::vector<int32_t> nsec_to_bsec(b->n.sectors.size(), -1);
+    for (int s = 0; s < S; ++s) nsec_to_bsec[b->sectors[s].n_sector] = s;
+    const auto &rec = h->j->rec[FOTCI_JUMP_N1];
+    auto slot = [&](const JumpRec &r) -> int64_t {
+        const int s = nsec_to_bsec[b->n.sd_sector[r.dst]];
+        const int qn = cl.class_of[r.label];
+        const int ch = b->n.sd_local[r.src] / kCH;
+        return ((int64_t)s * nq + qn) * nch + ch;
+    };
+    for (const auto &r : rec) cnt[slot(r) + 1]++;
+    for (size_t i = 0; i + 1 < cnt.size(); ++i) cnt[i + 1] += cnt[i];
+    t.pn_ptr.assign(cnt.begin(), cnt.end());
+    t.pn_code.assign(rec.size(), 0u);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (const auto &r : rec) {
+        const int64_t sl = slot(r);
+        const uint32_t dcol = (uint32_t)b->n.sd_local[r.dst];
+        const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kCH);
+        const uint32_t B = (uint32_t)cl.local_of[r.label];
+        t.pn_code[fill[sl]++] = (dcol << 14) | (so << 7) | ((B & 63u) << 1) | (r.phase < 0 ? 1u : 0u);
+    }
+    if (cnt.back() > INT32_MAX) ok = false;
+    t.ok = ok;
     const int npsd = (int)b->p.sd.size();
     t.order.resize(npsd);
     for (int i = 0; i < npsd; ++i) t.order[i] = i;
@@ -258,11 +326,35 @@ std::vector<Item> items(fotci_ham *h) {
     HostTiled &tt = h->tt;
     DevTiled &dt = h->dev_tiled;
     dt.ok = tt.ok ? 1 : 0;
+    dt.nn_ell_len = (int64_t)tt.nn_ell_src.size();
+    dt.pp_ell_len = (int64_t)tt.pp_ell_src.size();
+    dt.n_rtiles = (int32_t)tt.rt_sec.size();
+    dt.n_ctiles = (int32_t)tt.ct_sec.size();
+    dt.rt_rows = 8;
+    dt.ct_cols = 8;
+    dt.n_chunk = std::max(tt.n_chunk, 1);
+    dt.max_nn = tt.max_nn;
+    dt.max_np = tt.max_np;
     add(tt.order.data(), tt.order.size() * 4, &dt.order);
-    add(tt.p_off_base.data(), tt.p_off_base.size() * 8, &dt.p_off_base);
     add(tt.p_ob_base.data(), tt.p_ob_base.size() * 8, &dt.p_ob_base);
-    add(tt.n_off_local.data(), tt.n_off_local.size() * 4, &dt.n_off_local);
-    add(tt.n_ob_code.data(), tt.n_ob_code.size() * 4, &dt.n_ob_code);
+    add(tt.nn_ell_base.data(), tt.nn_ell_base.size() * 8, &dt.nn_ell_base);
+    add(tt.nn_ell_E.data(), tt.nn_ell_E.size() * 4, &dt.nn_ell_E);
+    add(tt.nn_ell_src.data(), tt.nn_ell_src.size() * 4, &dt.nn_ell_src);
+    add(tt.nn_ell_ent.data(), tt.nn_ell_ent.size() * 4, &dt.nn_ell_ent);
+    add(nullptr, tt.nn_ell_src.size() * 8, &dt.nn_ell_v64);
+    add(nullptr, tt.nn_ell_src.size() * 4, &dt.nn_ell_v32);
+    add(tt.pp_ell_base.data(), tt.pp_ell_base.size() * 8, &dt.pp_ell_base);
+    add(tt.pp_ell_E.data(), tt.pp_ell_E.size() * 4, &dt.pp_ell_E);
+    add(tt.pp_ell_src.data(), tt.pp_ell_src.size() * 4, &dt.pp_ell_src);
+    add(tt.pp_ell_ent.data(), tt.pp_ell_ent.size() * 4, &dt.pp_ell_ent);
+    add(nullptr, tt.pp_ell_src.size() * 8, &dt.pp_ell_v64);
+    add(nullptr, tt.pp_ell_src.size() * 4, &dt.pp_ell_v32);
+    add(tt.rt_sec.data(), tt.rt_sec.size() * 4, &dt.rt_sec);
+    add(tt.rt_r0.data(), tt.rt_r0.size() * 4, &dt.rt_r0);
+    add(tt.ct_sec.data(), tt.ct_sec.size() * 4, &dt.ct_sec);
+    add(tt.ct_c0.data(), tt.ct_c0.size() * 4, &dt.ct_c0);
+    add(tt.pn_ptr.data(), tt.pn_ptr.size() * 4, &dt.pn_ptr);
+    add(tt.pn_code.data(), tt.pn_code.size() * 4, &dt.pn_code);
     for (int sp = 0; sp < 2; ++sp) {
         HostSpeciesTables &t = sp == 0 ? h->tp : h->tn;
         DevSpecies &ds = sp == 0 ? d.p : d.n;
@@ -352,7 +444,7 @@ extern "C" int fotci_ham_upload_impl(fotci_ham *h, void *ws, int64_t bytes, void
     }
     h->ws = ws;
     h->ws_bytes = bytes;
-    launch_materialize(h->dev, stream);
+    launch_materialize(h, stream);
     hip_check(hipStreamSynchronize(st), "upload sync");
     h->uploaded = true;
     return FOTCI_OK;
@@ -376,7 +468,7 @@ extern "C" int fotci_ham_set_values_impl(fotci_ham *h, const double *spe_p, cons
             hip_check(hipMemcpyAsync((void *)ds.v2, t.v2.data(), t.v2.size() * 8, hipMemcpyHostToDevice, st),
                       "upload");
         }
-        launch_materialize(h->dev, stream);
+        launch_materialize(h, stream);
         hip_check(hipStreamSynchronize(st), "upload sync");
     }
     return FOTCI_OK;

@@ -130,7 +130,8 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_materialize(const DevHam &d, void *stream) {
+void launch_materialize(const fotci_ham *h, void *stream) {
+    const DevHam &d = h->dev;
     hipStream_t st = (hipStream_t)stream;
     for (const DevSpecies *s : {&d.p, &d.n}) {
         if (s->n_off > 0) hipLaunchKernelGGL(k_mat_off, dim3(blocks_for(s->n_off, 256)), dim3(256), 0, st, *s);
@@ -139,6 +140,7 @@ void launch_materialize(const DevHam &d, void *stream) {
     if (d.n_vq > 0)
         hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(d.n_vq, 256)), dim3(256), 0, st, d.vq64, d.vq32, d.n_vq);
     hip_check(hipGetLastError(), "materialize launch");
+    launch_materialize_tiled(d, h->dev_tiled, stream);
 }
 
 // The plain kernel in float64 (FOTCI_MODE_F64_PLAIN) or float32 (used for

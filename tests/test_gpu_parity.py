@@ -88,8 +88,10 @@ def test_hermitian_and_deterministic():
     hg = h.apply(g)
     a, b = float(g @ hx), float(hg @ x)
     assert abs(a - b) <= 1e-12 * abs(a)
-    assert torch.equal(hx, h.apply(x))
+    # the plain kernel is a pure gather: bitwise reproducible; the tiled pn
+    # kernel sums through LDS atomics, so only rounding-level agreement
     assert torch.equal(h.apply(x, mode="f64_plain"), h.apply(x, mode="f64_plain"))
+    assert float((hx - h.apply(x)).norm() / hx.norm()) < 1e-14
 
 
 @pytest.mark.parametrize("space,Z,N,two_M,par,opar", [
