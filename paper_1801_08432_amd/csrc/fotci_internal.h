@@ -159,20 +159,24 @@ struct DevTiled {
     const int32_t *rt_sec, *rt_r0;   // [n_rtiles] row tiles (nn kernel)
     const int32_t *ct_sec, *ct_c0;   // [n_ctiles] column tiles (pp kernel)
     int32_t n_rtiles, n_ctiles, rt_rows, ct_cols;
-    // pn neutron gather lists grouped by (destination sector, neutron class, source chunk)
-    const int32_t *pn_ptr;       // [(n_sectors*nq)*n_chunk + 1]
-    const uint32_t *pn_code;     // (dst col << 14) | (src col - chunk start) << 7 | B << 1 | (phase < 0)
-    int32_t n_chunk;             // chunks per sector slot (ceil(max nn / 128))
+    // pn neutron gather lists grouped by (destination sector, neutron class, 16-column source tile)
+    const int32_t *pn_ptr;       // [(n_sectors*nq)*n_t16 + 1]
+    const uint32_t *pn_code;     // (dst col << 11) | (B << 5) | (src col - tile start) << 1 | (phase < 0);
+                                 // kNullCode pads rounds of 64 entries with distinct destinations
+    int32_t n_t16;               // tiles per sector slot (ceil(max nn / 16))
+    int32_t kp_pad;              // max proton one-body jumps into a row per class, rounded up to 4
     int32_t max_nn, max_np;
     int32_t ok;
 };
+
+constexpr uint32_t kNullCode = 0xffffffffu;
 
 struct HostTiled {
     std::vector<int32_t> order, nn_ell_E, nn_ell_src, nn_ell_ent, pp_ell_E, pp_ell_src, pp_ell_ent;
     std::vector<int64_t> p_ob_base, nn_ell_base, pp_ell_base;
     std::vector<int32_t> rt_sec, rt_r0, ct_sec, ct_c0, pn_ptr;
     std::vector<uint32_t> pn_code;
-    int n_chunk = 0, max_nn = 0, max_np = 0;
+    int n_t16 = 0, kp_pad = 4, max_nn = 0, max_np = 0;
     bool ok = false;
 };
 

@@ -86,7 +86,7 @@ void build_tiled_tables(fotci_ham *h) {
     const int nq = cl.nq;
     const int S = (int)b->sectors.size();
     HostTiled &t = h->tt;
-    constexpr int kCH = 128;   // source chunk of the pn kernel
+    constexpr int kTL = 16;    // source tile of the pn kernel
     bool ok = true;
     for (int q = 0; q < nq; ++q)
         if (cl.ops[q].size() > 64) ok = false;
@@ -97,6 +97,7 @@ void build_tiled_tables(fotci_ham *h) {
     }
     // LDS tiles hold up to 64 KiB of float64 (8 rows / columns of the largest sector)
     if ((int64_t)t.max_nn * 8 > 65536 || (int64_t)t.max_np * 8 > 65536 || t.max_nn >= (1 << 18)) ok = false;
+    // the pn kernel keeps one output row and the contraction operand in LDS
     t.ok = ok;
     t.p_ob_base.resize(h->tp.ob_src.size());
     for (size_t k = 0; k < h->tp.ob_src.size(); ++k) t.p_ob_base[k] = b->pstart[h->tp.ob_src[k]];
@@ -142,32 +143,77 @@ void build_tiled_tables(fotci_ham *h) {
         }
     }
     // pn gather lists: neutron one-body jumps into the columns of each
-    // destination sector, grouped by (neutron class, source chunk)
-    t.n_chunk = (t.max_nn + kCH - 1) / kCH;
-    const int nch = std::max(t.n_chunk, 1);
-    std::vector<int64_t> cnt((size_t)S * nq * nch + 1, 0);
+    // destination sector, grouped by (neutron class, 16-column source tile)
+    t.n_t16 = (t.max_nn + kTL - 1) / kTL;
+    const int nch = std::max(t.n_t16, 1);
+    int kpmax = 1;
+    for (size_t i = 0; i + 1 < h->tp.ob_ptr.size(); ++i) kpmax = std::max(kpmax, h->tp.ob_ptr[i + 1] - h->tp.ob_ptr[i]);
+    t.kp_pad = (kpmax + 3) & ~3;
+    // up to 32 proton jumps per class in the pn kernel; x addressed with 32-bit byte offsets
+    if (kpmax > 32 || b->dim * 8 >= ((int64_t)1 << 31) || t.max_nn >= (1 << 21)) ok = false;
     std::vector<int32_t> nsec_to_bsec(b->n.sectors.size(), -1);
     for (int s = 0; s < S; ++s) nsec_to_bsec[b->sectors[s].n_sector] = s;
     const auto &rec = h->j->rec[FOTCI_JUMP_N1];
     auto slot = [&](const JumpRec &r) -> int64_t {
         const int s = nsec_to_bsec[b->n.sd_sector[r.dst]];
         const int qn = cl.class_of[r.label];
-        const int ch = b->n.sd_local[r.src] / kCH;
+        const int ch = b->n.sd_local[r.src] / kTL;
         return ((int64_t)s * nq + qn) * nch + ch;
     };
+    // group the jumps by slot, ordered inside a slot by (source, label)
+    std::vector<int64_t> cnt((size_t)S * nq * nch + 1, 0);
     for (const auto &r : rec) cnt[slot(r) + 1]++;
     for (size_t i = 0; i + 1 < cnt.size(); ++i) cnt[i + 1] += cnt[i];
-    t.pn_ptr.assign(cnt.begin(), cnt.end());
-    t.pn_code.assign(rec.size(), 0u);
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (const auto &r : rec) {
-        const int64_t sl = slot(r);
-        const uint32_t dcol = (uint32_t)b->n.sd_local[r.dst];
-        const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kCH);
-        const uint32_t B = (uint32_t)cl.local_of[r.label];
-        t.pn_code[fill[sl]++] = (dcol << 14) | (so << 7) | ((B & 63u) << 1) | (r.phase < 0 ? 1u : 0u);
+    std::vector<size_t> order(rec.size());
+    {
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        std::vector<size_t> by_src(rec.size());
+        for (size_t i = 0; i < rec.size(); ++i) by_src[i] = i;
+        std::stable_sort(by_src.begin(), by_src.end(), [&](size_t x, size_t y) {
+            if (rec[x].src != rec[y].src) return rec[x].src < rec[y].src;
+            return rec[x].label < rec[y].label;
+        });
+        for (size_t i : by_src) order[fill[slot(rec[i])]++] = i;
     }
-    if (cnt.back() > INT32_MAX) ok = false;
+    // Pack each slot into rounds of 64 entries with distinct destination
+    // columns (one round = one LDS atomic instruction of a wave, so no two
+    // lanes add to the same address); every round but the last is padded
+    // with null codes to 64 entries.
+    t.pn_ptr.assign(cnt.size(), 0);
+    t.pn_code.clear();
+    std::vector<std::vector<uint32_t>> rounds;
+    std::vector<std::vector<uint32_t>> round_dst;
+    for (size_t sl = 0; sl + 1 < cnt.size(); ++sl) {
+        t.pn_ptr[sl] = (int64_t)t.pn_code.size();
+        rounds.clear();
+        round_dst.clear();
+        for (int64_t k = cnt[sl]; k < cnt[sl + 1]; ++k) {
+            const auto &r = rec[order[k]];
+            const uint32_t dcol = (uint32_t)b->n.sd_local[r.dst];
+            const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kTL);
+            const uint32_t B = (uint32_t)cl.local_of[r.label];
+            // (destination column << 11) | (B << 5) | (source offset in the tile << 1) | sign
+            const uint32_t code = (dcol << 11) | ((B & 63u) << 5) | (so << 1) | (r.phase < 0 ? 1u : 0u);
+            size_t g = 0;
+            for (; g < rounds.size(); ++g) {
+                if (rounds[g].size() >= 64) continue;
+                if (std::find(round_dst[g].begin(), round_dst[g].end(), dcol) == round_dst[g].end()) break;
+            }
+            if (g == rounds.size()) {
+                rounds.emplace_back();
+                round_dst.emplace_back();
+            }
+            rounds[g].push_back(code);
+            round_dst[g].push_back(dcol);
+        }
+        for (size_t g = 0; g < rounds.size(); ++g) {
+            for (uint32_t c : rounds[g]) t.pn_code.push_back(c);
+            if (g + 1 < rounds.size())
+                for (size_t p = rounds[g].size(); p < 64; ++p) t.pn_code.push_back(kNullCode);
+        }
+    }
+    t.pn_ptr[cnt.size() - 1] = (int64_t)t.pn_code.size();
+    if ((int64_t)t.pn_code.size() > INT32_MAX) ok = false;
     t.ok = ok;
     const int npsd = (int)b->p.sd.size();
     t.order.resize(npsd);
@@ -332,7 +378,8 @@ std::vector<Item> items(fotci_ham *h) {
     dt.n_ctiles = (int32_t)tt.ct_sec.size();
     dt.rt_rows = 8;
     dt.ct_cols = 8;
-    dt.n_chunk = std::max(tt.n_chunk, 1);
+    dt.n_t16 = std::max(tt.n_t16, 1);
+    dt.kp_pad = tt.kp_pad;
     dt.max_nn = tt.max_nn;
     dt.max_np = tt.max_np;
     add(tt.order.data(), tt.order.size() * 4, &dt.order);

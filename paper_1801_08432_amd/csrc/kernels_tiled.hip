@@ -19,10 +19,11 @@
 //              R[B, jn] = sum_k (phase_k V^q[A_k, B]) x[ip_k, jn]
 //            over the K_p proton one-body jumps (ip_k -> ip', label A_k) is a
 //            dense contraction on the matrix cores (M = neutron labels B, N =
-//            source neutron columns jn, K = proton jumps), staged in LDS 128
-//            source columns at a time; the neutron one-body jumps whose
-//            source lies in that chunk (pre-grouped by chunk, read coalesced)
-//            then add phase_l R[B_l, jn_l] into the output row held in LDS.
+//            source neutron columns jn, K = proton jumps); each wave takes
+//            16-column source tiles, keeps its R tile in LDS, and the neutron
+//            one-body jumps whose source lies in the tile (pre-grouped by
+//            tile, read coalesced) add phase_l R[B_l, jn_l] into the output
+//            row held in LDS.
 //            This is the proton-first grouping of sum_{A,B} V_AB P_A X N_B^T:
 //            the contraction over B is dense, so the matrix cores execute
 //            about n_B / (neutron jumps per column) ~ 5 times the useful
@@ -40,9 +41,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;      // threads per workgroup (4 waves)
 constexpr int kTile = 8;     // rows (nn kernel) / columns (pp kernel) per tile
-constexpr int kCH = 128;     // source columns per LDS chunk of R
 constexpr int kNB = 64;      // max neutron labels per class (rows of R)
-constexpr int kKB = 32;      // proton jumps per contraction batch
 constexpr int kLdsTile = 65536;  // bytes of LDS for a staged tile
 
 template <typename T>
@@ -187,24 +186,141 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
 }
 
 // ---------------------------------------------------------------------- pn
+// Waves work independently on 16-column source tiles: each contracts its tile
+// on the matrix cores into a wave-private slice of R in LDS and gathers the
+// neutron jumps whose source lies in the tile into the shared output row.
+// Only the per-class staging of C needs a workgroup barrier. x is read with
+// buffer loads: each lane's offset is fixed for the whole class and the tile
+// offset is scalar; padding lanes point past the end of x and read zero.
+constexpr unsigned kBufFlags = 0x00020000u;   // raw buffer, 32-bit data format
+constexpr unsigned kOutOfRange = 0x7ff00000u;  // byte offset beyond any x
+
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+// flip the sign of v when the low bit of code is set
+__device__ __forceinline__ float signed_by(float v, uint32_t code) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ (code << 31));
+}
+__device__ __forceinline__ double signed_by(double v, uint32_t code) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)code << 63));
+}
+
+constexpr int kKP = 32;   // max proton one-body jumps into one row per class
+
+// LDS strides chosen so that the matrix-core operand reads (16 rows of C
+// per k-slot) and the R tile stores hit distinct banks in each half-wave.
+template <typename T>
+struct Lds;
+template <>
+struct Lds<float> {
+    static constexpr int c_stride = 34;   // 2*col + k spans all 32 banks
+    static constexpr int r_stride = 20;   // rows 4 apart land 16 banks apart
+};
+template <>
+struct Lds<double> {
+    static constexpr int c_stride = 33;
+    static constexpr int r_stride = 16;
+};
+
+// One wave's tiles of one class, specialised on the number of 16-row tiles
+// of neutron labels (NBT) and of 4-jump k-steps (KST) so the inner loop has
+// no runtime guards around the matrix-core instructions.
+template <typename T, int NBT, int KST>
+__device__ __forceinline__ void pn_tiles(const T *__restrict__ Cl, const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+                                         const int32_t *__restrict__ pnp, const uint32_t *__restrict__ pnc, int ntiles,
+                                         int wid, int lane, int col_l, T *__restrict__ R, T *__restrict__ yl) {
+    typedef typename Mma<T>::acc_t acc_t;
+    for (int t = wid; t < ntiles; t += kT / 64) {
+        const int e0 = __builtin_amdgcn_readfirstlane(pnp[t]);
+        const int e1 = __builtin_amdgcn_readfirstlane(pnp[t + 1]);
+        if (e0 == e1) continue;
+        const unsigned soff = (unsigned)(16 * t) * (unsigned)sizeof(T);
+        T xv[KST];
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks) xv[ks] = buffer_load<T>(xr, voff[ks], soff);
+        const int ne = e1 - e0;
+        const uint32_t *codes = pnc + e0;
+        uint32_t cr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cr[i] = lane + 64 * i < ne ? codes[lane + 64 * i] : 0u;
+        acc_t acc[NBT];
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) acc[b] = Mma<T>::zero();
+        constexpr int CS = Lds<T>::c_stride, RS = Lds<T>::r_stride;
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks)
+#pragma unroll
+            for (int bt = 0; bt < NBT; ++bt) acc[bt] = Mma<T>::mma(Cl[bt * 16 * CS + 4 * ks], xv[ks], acc[bt]);
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) R[(16 * bt + Mma<T>::row(lane, r)) * RS + col_l] = acc[bt][r];
+        // a wave's LDS operations complete in issue order: the gather below
+        // sees the stores above without a workgroup barrier
+        __builtin_amdgcn_wave_barrier();
+        // code bits 5..10: neutron label B (row of R), bits 1..4: source column in the tile
+        // each round of 64 entries has distinct destinations (null codes pad
+        // it), so the lanes of one LDS atomic never hit the same address
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (lane + 64 * i < ne && cr[i] != kNullCode)
+                atomicAdd(&yl[cr[i] >> 11], signed_by(R[((cr[i] >> 5) & 63u) * RS + ((cr[i] >> 1) & 15u)], cr[i]));
+        for (int i = lane + 256; i < ne; i += 64) {
+            const uint32_t code = codes[i];
+            if (code != kNullCode)
+                atomicAdd(&yl[code >> 11], signed_by(R[((code >> 5) & 63u) * RS + ((code >> 1) & 15u)], code));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <typename T, int NBT>
+__device__ __forceinline__ void pn_tiles_k(int ksteps, const T *Cl, const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+                                           const int32_t *pnp, const uint32_t *pnc, int ntiles, int wid, int lane,
+                                           int col_l, T *R, T *yl) {
+    switch (ksteps) {
+        case 1: pn_tiles<T, NBT, 1>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        case 2: pn_tiles<T, NBT, 2>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        case 3: pn_tiles<T, NBT, 3>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        case 4: pn_tiles<T, NBT, 4>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        case 5: pn_tiles<T, NBT, 5>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        case 6: pn_tiles<T, NBT, 6>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        case 7: pn_tiles<T, NBT, 7>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        default: pn_tiles<T, NBT, 8>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
-    typedef typename Mma<T>::acc_t acc_t;
-    __shared__ T R[kNB * kCH];
-    __shared__ T C[kNB * kKB];
-    __shared__ int64_t srcb[kKB];
+    constexpr int CS = Lds<T>::c_stride;
+    __shared__ T Rw[kT / 64][kNB * Lds<T>::r_stride];
+    __shared__ T C[kNB * CS];
+    __shared__ int32_t srcb[kKP];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *yl = reinterpret_cast<T *>(smem_raw);   // output row [nn]
 
     const int ip = TT.order[blockIdx.x];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wid = tid >> 6;
+    // the wave index is uniform across the wave: keep it (and the tile loop) scalar
+    const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col_l = lane & 15, kq = lane >> 4;
     const int s = P.p_sector[ip];
     const int nn = P.sec_nn[s];
     const int64_t base = P.p_pstart[ip];
     const int nq = P.nq;
-    const int nch = TT.n_chunk;
+    const int ntl = TT.n_t16;
     const T *vq = TabT<T>::vq(P);
+    const __amdgpu_buffer_rsrc_t xr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)sizeof(T)), kBufFlags);
+    T *R = Rw[wid];
     for (int c = tid; c < nn; c += kT) yl[c] = 0;
     bool any = false;
     for (int q = 0; q < nq; ++q) {
@@ -216,76 +332,37 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
         const int nbt = (nB + 15) >> 4;
         const T *V = vq + P.vq_off[q];
         const int nns = P.sec_nn[P.p_sector[P.p.ob_src[a0]]];
-        const int64_t pslot = ((int64_t)s * nq + qn) * nch;
+        const int64_t pslot = ((int64_t)s * nq + qn) * ntl;
         const int kp = a1 - a0;
-        const int nbat = (kp + kKB - 1) / kKB;
-        // stage the contraction operand C[B][k] = phase_k V^q[A_k, B] and the
-        // source row offsets of one batch of proton jumps
-        auto stage = [&](int kb0, int kn) {
-            __syncthreads();
-            for (int t = tid; t < kn; t += kT) srcb[t] = TT.p_ob_base[kb0 + t];
-            for (int idx = tid; idx < kNB * kKB; idx += kT) {
-                const int B = idx / kKB, k = idx - B * kKB;
-                T v = 0;
-                if (B < nB && k < kn) {
-                    const int code = P.p.ob_code[kb0 + k];
-                    v = V[(code >> 1) * nB + B];
-                    if (code & 1) v = -v;
-                }
-                C[idx] = v;
+        // C[B][k] = phase_k V^q[A_k, B] and the source row offsets
+        __syncthreads();
+        for (int t = tid; t < kKP; t += kT) srcb[t] = t < kp ? (int32_t)TT.p_ob_base[a0 + t] : -1;
+        for (int idx = tid; idx < kNB * CS; idx += kT) {
+            const int B = idx / CS, k = idx - B * CS;
+            T v = 0;
+            if (B < nB && k < kp) {
+                const int code = P.p.ob_code[a0 + k];
+                v = V[(code >> 1) * nB + B];
+                if (code & 1) v = -v;
             }
-            __syncthreads();
-        };
-        if (nbat == 1) stage(a0, kp);
-        for (int c0 = 0, ch = 0; c0 < nns; c0 += kCH, ++ch) {
-            const int e0 = TT.pn_ptr[pslot + ch], e1 = TT.pn_ptr[pslot + ch + 1];
-            if (e0 == e1) continue;   // no neutron jump starts in this chunk (uniform)
-            acc_t t0[4], t1[4];
+            C[idx] = v;
+        }
+        __syncthreads();
+        const int ksteps = (kp + 3) >> 2;
+        const int ntiles = (nns + 15) >> 4;
+        unsigned voff[8];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) t0[b] = t1[b] = Mma<T>::zero();
-            for (int bat = 0; bat < nbat; ++bat) {
-                const int kb0 = a0 + bat * kKB;
-                const int kn = min(kKB, a1 - kb0);
-                if (nbat > 1) stage(kb0, kn);
-                const int ksteps = (kn + 3) >> 2;
-                const int col0 = c0 + 16 * wid + (lane & 15);
-                const int col1 = col0 + 64;
-                for (int ks = 0; ks < ksteps; ++ks) {
-                    const int k = 4 * ks + (lane >> 4);
-                    T b0 = 0, b1 = 0;
-                    if (k < kn) {
-                        const int64_t sb = srcb[k];
-                        if (col0 < nns) b0 = x[sb + col0];
-                        if (col1 < nns) b1 = x[sb + col1];
-                    }
-#pragma unroll
-                    for (int bt = 0; bt < 4; ++bt) {
-                        if (bt < nbt) {
-                            const T a = C[(16 * bt + (lane & 15)) * kKB + k];
-                            t0[bt] = Mma<T>::mma(a, b0, t0[bt]);
-                            t1[bt] = Mma<T>::mma(a, b1, t1[bt]);
-                        }
-                    }
-                }
-            }
-            __syncthreads();   // the previous chunk's gather has finished reading R
-#pragma unroll
-            for (int bt = 0; bt < 4; ++bt) {
-                if (bt < nbt) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = 16 * bt + Mma<T>::row(lane, r);
-                        R[row * kCH + 16 * wid + (lane & 15)] = t0[bt][r];
-                        R[row * kCH + 64 + 16 * wid + (lane & 15)] = t1[bt][r];
-                    }
-                }
-            }
-            __syncthreads();
-            for (int e = e0 + tid; e < e1; e += kT) {
-                const uint32_t code = TT.pn_code[e];
-                const T v = R[((code >> 1) & 63u) * kCH + ((code >> 7) & 127u)];
-                atomicAdd(&yl[code >> 14], (code & 1u) ? -v : v);
-            }
+        for (int ks = 0; ks < 8; ++ks) {
+            const int sb = srcb[4 * ks + kq];
+            voff[ks] = sb >= 0 ? (unsigned)(sb + col_l) * (unsigned)sizeof(T) : kOutOfRange;
+        }
+        const T *Cl = C + col_l * CS + kq;
+        const int32_t *pnp = TT.pn_ptr + pslot;
+        switch (nbt) {
+            case 1: pn_tiles_k<T, 1>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
+            case 2: pn_tiles_k<T, 2>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
+            case 3: pn_tiles_k<T, 3>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
+            default: pn_tiles_k<T, 4>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
         }
     }
     if (!any) return;
@@ -317,7 +394,8 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
         case 2: hipLaunchKernelGGL((k_pp<T, 2>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
         default: hipLaunchKernelGGL((k_pp<T, 1>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
     }
-    hipLaunchKernelGGL(k_pn<T>, dim3(d.p.n_sd), dim3(kT), (size_t)t.max_nn * sizeof(T), st, d, t, x, y);
+    const size_t lds_pn = (size_t)t.max_nn * sizeof(T);
+    hipLaunchKernelGGL(k_pn<T>, dim3(d.p.n_sd), dim3(kT), lds_pn, st, d, t, x, y);
 }
 
 }  // namespace
