@@ -2,14 +2,18 @@
 
 A step is one apply_H (diagonal + pp + nn + pn, every jump applied) in the
 chosen arithmetic mode on the 20-m-state space with 5 protons and 5 neutrons
-at M = 0 (dim 18,600,516), inputs resident in HBM. After the timed steps
-the script runs the Lanczos comparison the metric asks for (float32-vector
-path against the float64 path, lowest 10 of 200 iterations) and times the
-CPU oracle on a bounded sample of rows. One JSON line is printed.
+at M = 0 (dim 18,600,516), inputs resident in HBM. The library records HIP
+events between its kernels on the launch stream during the timed steps, which
+gives the duration of the dominant kernel (pn) for the roofline object. After
+the timed steps the script runs the Lanczos comparison the metric asks for
+(float32-vector path against the plain float64 path, lowest 10 of 200
+iterations; the tiled float64 path beside them) and times the CPU oracle on a
+bounded sample of rows. One JSON line is printed.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +30,31 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """Hash of the tiled kernel source: stored PMC traffic is used only for this exact source."""
+    path = os.path.join(ROOT, "paper_1801_08432_amd", "csrc", "kernels_tiled.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def stored_traffic(mode):
+    """HBM bytes per k_pn launch from the committed PMC summary, or None.
+
+    The summary (profiles/pn_traffic_pf_5p5n.txt) holds lines
+    'source_hash <h>' and '<mode> bytes_per_launch <B>'; values are used only
+    when the hash matches the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "pn_traffic_pf_5p5n.txt")
+    if not os.path.exists(path):
+        return None
+    h, val = None, None
+    for line in open(path):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "source_hash":
+            h = f[1]
+        if len(f) >= 3 and f[0] == mode and f[1] == "bytes_per_launch":
+            val = float(f[2])
+    return val if h == kernel_source_hash() else None
 
 
 def cpu_baseline(w, x, seconds):
@@ -64,6 +93,8 @@ def main():
     ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also copy 1 GiB (float32) once, a known-size kernel for HBM counter calibration")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on exactly one GPU: the path is built and measured on one "
@@ -96,6 +127,7 @@ def main():
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    h.profile_start(a.steps)
     t0 = time.perf_counter()
     ev0.record()
     for _ in range(a.steps):
@@ -103,22 +135,37 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t0
-    t_kernel = ev0.elapsed_time(ev1) / 1e3 / a.steps
+    kernels_ms, n_prof = h.profile_stop()
+    t_events = ev0.elapsed_time(ev1) / 1e3 / a.steps
     ms_per_step = 1e3 * t_wall / a.steps
-    log("[bench] %s: %.3f ms/apply wall, %.3f ms/apply (events)" % (mode, ms_per_step, 1e3 * t_kernel))
+    log("[bench] %s: %.3f ms/apply wall, %.3f ms/apply (events); kernels %s" %
+        (mode, ms_per_step, 1e3 * t_events, {k: round(v, 4) for k, v in kernels_ms.items()}))
 
-    # algorithmic bytes per apply under the per-operation streamed model:
-    # every operation reads one x element, y is written once, jump tables once
-    table_bytes = h.workspace_bytes()
-    streamed = n_ops * es + h.dim * es + table_bytes
-    compulsory = 2 * h.dim * es + table_bytes
-    achieved = streamed / t_kernel / 1e9
+    # Roofline of the dominant kernel. Algorithmic bytes per launch under the
+    # per-operation streamed model: every multiply-add reads one x element,
+    # y is read and written once, the kernel's jump tables are read once.
+    dom = "k_pn" if "k_pn" in kernels_ms else max(kernels_ms, key=kernels_ms.get)
+    t_dom = kernels_ms[dom] / 1e3
+    n_p1 = h.jumps.count(fotci.JUMP_P1)
+    n_n1 = h.jumps.count(fotci.JUMP_N1)
+    if dom == "k_pn":
+        dom_ops = ops["pn"]
+        tables = n_p1 * 12 + n_n1 * 4 + h.basis.n_psd * 64 * 4
+        y_bytes = 2 * h.dim * es
+    else:
+        dom_ops = n_ops
+        tables = h.workspace_bytes()
+        y_bytes = h.dim * es
+    streamed = dom_ops * es + y_bytes + tables
+    achieved = streamed / t_dom / 1e9
+    traffic = stored_traffic(mode)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                model="streamed: ops*%dB + dim*%dB + tables (%.3g B/apply); compulsory %.3g B/apply" %
-                      (es, es, streamed, compulsory),
-                compulsory_gbs=round(compulsory / t_kernel / 1e9, 2),
-                useful_gflops=round(2 * n_ops / t_kernel / 1e9, 1))
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel=dom, kernel_ms=round(1e3 * t_dom, 4),
+                model="streamed: %s ops*%dB + y %dB + tables %dB = %.4g B/launch" % (dom, es, y_bytes, tables,
+                                                                                     streamed),
+                useful_gflops=round(2 * dom_ops / t_dom / 1e9, 1),
+                compulsory_gbs=round((h.dim * es + y_bytes + tables) / t_dom / 1e9, 1))
 
     out = {"metric": METRIC, "value": round(1.0 / (t_wall / a.steps), 3), "unit": "apply_H/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -126,12 +173,20 @@ def main():
            "config": {"workload": "%s (2j=%s, %dp%dn, 2M=%d, dim %d)" % (a.workload, list(w["two_j"]), w["Z"],
                                                                       w["N"], w["two_M"], h.dim),
                       "mode": mode, "ops_per_apply": n_ops, "setup_s": round(t_setup, 2)},
+           "kernels_ms": {k: round(v, 4) for k, v in kernels_ms.items()},
            "roofline": roof}
 
+    if a.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not a.no_lanczos:
         piv = torch.from_numpy(inputs.random_vector(h.dim, 1802)).to(dev)
         res = {}
-        for m in (mode, "f64_plain"):
+        for m in (mode, "f64", "f64_plain"):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = h.lanczos_lowest(piv, 10, a.lanczos_iters, mode=m)
@@ -144,7 +199,9 @@ def main():
                               s_per_iter={m: round(res[m][1] / a.lanczos_iters, 5) for m in res},
                               max_rel_eig_err=float(rel.max()),
                               max_resid={m: float(res[m][0]["resid"].max()) for m in res},
-                              speedup_vs_f64_plain=round(res["f64_plain"][1] / res[mode][1], 3))
+                              speedup_vs_f64_plain=round(res["f64_plain"][1] / res[mode][1], 3),
+                              f64_tiled_rel_err_vs_plain=float(np.max(np.abs(res["f64"][0]["evals"] - e64) /
+                                                                       np.abs(e64))))
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, xs, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -40,8 +40,7 @@ extern "C" {
 /* Arithmetic modes of apply_H / lanczos_lowest. */
 #define FOTCI_MODE_F64_PLAIN 0  /* float64 vectors; straightforward gather kernel */
 #define FOTCI_MODE_F64 1        /* float64 vectors; tiled kernels */
-#define FOTCI_MODE_F32 2        /* float32 vectors and matrix elements */
-#define FOTCI_MODE_BF16X3 3     /* float32 vectors; pn contraction on bf16 MFMA, 3-term split */
+#define FOTCI_MODE_F32 2        /* float32 vectors and matrix elements (pn on f32 MFMA) */
 
 /* Jump kinds for fotci_jumps_count / fotci_jumps_export. */
 #define FOTCI_JUMP_PP2 0  /* proton two-body jumps */
@@ -210,6 +209,20 @@ int fotci_lanczos_lowest(const fotci_ham *h, const fotci_lanczos_opts *o, const 
  * "operations" (Ch. 8, "Jump storage"). */
 int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn,
                         int64_t *ops_diag);
+
+/*
+ * fotci_profile_start / fotci_profile_stop -- per-kernel timing of apply_H
+ * (the paper's "mode times", Ch. 8, done with HIP events). Between start and
+ * stop, every fotci_apply_H call on this Hamiltonian records a HIP event on
+ * its stream before its first kernel and after each kernel (max_calls calls at
+ * most; later calls are not recorded). stop synchronises on the events and
+ * writes, for each kernel of the last recorded mode, the mean duration in
+ * milliseconds (avg_ms[k], k < *n_kernels <= 4) and its name (names[k],
+ * static strings; names may be NULL); *n_calls = calls recorded. The events
+ * are host-side HIP objects created by start and destroyed by stop.
+ */
+int fotci_profile_start(fotci_ham *h, int32_t max_calls);
+int fotci_profile_stop(fotci_ham *h, double *avg_ms, const char **names, int32_t *n_kernels, int32_t *n_calls);
 
 /*
  * Host utility: eigenvalues (ascending) and orthonormal eigenvectors of the

@@ -207,6 +207,53 @@ int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, in
     return guard([&] { return fotci_ham_op_counts_impl(h, ops_pp, ops_nn, ops_pn, ops_diag); });
 }
 
+int fotci_profile_start(fotci_ham *h, int32_t max_calls) {
+    return guard([&] {
+        if (!h || max_calls < 1) fail(FOTCI_EINVAL, "bad argument");
+        auto &pr = h->prof;
+        for (void *e : pr.events) (void)hipEventDestroy((hipEvent_t)e);
+        pr.events.assign((size_t)max_calls * 5, nullptr);
+        for (auto &e : pr.events) {
+            hipEvent_t ev;
+            hip_check(hipEventCreate(&ev), "hipEventCreate");
+            e = (void *)ev;
+        }
+        pr.max_calls = max_calls;
+        pr.calls = 0;
+        pr.n_kernels = 0;
+        pr.on = true;
+        return FOTCI_OK;
+    });
+}
+
+int fotci_profile_stop(fotci_ham *h, double *avg_ms, const char **names, int32_t *n_kernels, int32_t *n_calls) {
+    return guard([&] {
+        if (!h) fail(FOTCI_EINVAL, "NULL handle");
+        auto &pr = h->prof;
+        pr.on = false;
+        double acc[4] = {0, 0, 0, 0};
+        for (int c = 0; c < pr.calls; ++c) {
+            void **ev = &pr.events[(size_t)c * 5];
+            hip_check(hipEventSynchronize((hipEvent_t)ev[pr.n_kernels]), "hipEventSynchronize");
+            for (int k = 0; k < pr.n_kernels; ++k) {
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, (hipEvent_t)ev[k], (hipEvent_t)ev[k + 1]), "hipEventElapsedTime");
+                acc[k] += ms;
+            }
+        }
+        for (int k = 0; k < pr.n_kernels; ++k) {
+            if (avg_ms) avg_ms[k] = pr.calls ? acc[k] / pr.calls : 0.0;
+            if (names) names[k] = pr.names[k];
+        }
+        if (n_kernels) *n_kernels = pr.n_kernels;
+        if (n_calls) *n_calls = pr.calls;
+        for (void *e : pr.events) (void)hipEventDestroy((hipEvent_t)e);
+        pr.events.clear();
+        pr.calls = 0;
+        return FOTCI_OK;
+    });
+}
+
 int fotci_tridiag_eigh(int32_t n, const double *diag, const double *offdiag, double *evals, double *evecs) {
     return guard([&] {
         if (n < 1 || !diag || !evals) fail(FOTCI_EINVAL, "bad argument");

@@ -210,6 +210,14 @@ struct fotci_ham {
     void *ws = nullptr;
     int64_t ws_bytes = 0;
     fotci::DevHam dev{};
+    // per-kernel timing (fotci_profile_start/stop)
+    struct Profile {
+        bool on = false;
+        int max_calls = 0, calls = 0, n_kernels = 0;
+        std::vector<void *> events;   // hipEvent_t, (max_calls * 5)
+        const char *names[4] = {nullptr, nullptr, nullptr, nullptr};
+    };
+    mutable Profile prof;
     // layout (offsets in bytes from ws), filled by layout()
     std::vector<std::pair<std::string, int64_t>> layout_offsets;
     int64_t layout_total = 0;
@@ -227,7 +235,8 @@ void launch_materialize(const fotci_ham *h, void *stream);
 void launch_materialize_tiled(const DevHam &d, const DevTiled &t, void *stream);
 void launch_apply(const fotci_ham *h, int mode, const void *x, void *y, void *stream);
 void launch_apply_plain(const DevHam &d, int mode, const void *x, void *y, void *stream);
-void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream);
+void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream,
+                        void **events = nullptr);
 void build_tiled_tables(fotci_ham *h);
 void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g,
                 double *dx, double *d_spe_p, double *d_spe_n, double *d_v_pp, double *d_v_nn,

@@ -157,17 +157,33 @@ void launch_apply_plain(const DevHam &d, int mode, const void *x, void *y, void 
 }
 
 void launch_apply(const fotci_ham *h, int mode, const void *x, void *y, void *stream) {
+    auto &pr = h->prof;
+    void **ev = nullptr;
+    if (pr.on && pr.calls < pr.max_calls) ev = &pr.events[(size_t)pr.calls * 5];
     switch (mode) {
         case FOTCI_MODE_F64_PLAIN:
+            if (ev) hip_check(hipEventRecord((hipEvent_t)ev[0], (hipStream_t)stream), "event");
             launch_apply_plain(h->dev, mode, x, y, stream);
+            if (ev) {
+                hip_check(hipEventRecord((hipEvent_t)ev[1], (hipStream_t)stream), "event");
+                pr.n_kernels = 1;
+                pr.names[0] = "k_apply_plain";
+            }
             break;
         case FOTCI_MODE_F64:
         case FOTCI_MODE_F32:
-            launch_apply_tiled(h->dev, h->dev_tiled, mode, x, y, stream);
+            launch_apply_tiled(h->dev, h->dev_tiled, mode, x, y, stream, ev);
+            if (ev) {
+                pr.n_kernels = 3;
+                pr.names[0] = "k_nn_diag";
+                pr.names[1] = "k_pp";
+                pr.names[2] = "k_pn";
+            }
             break;
         default:
             fail(FOTCI_EINVAL, "unknown or unsupported mode");
     }
+    if (ev) pr.calls++;
 }
 
 }  // namespace fotci

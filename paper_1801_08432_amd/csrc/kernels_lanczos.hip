@@ -362,7 +362,6 @@ void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *
             run<double>(h, o, pivot, (char *)work, evals, resid, evecs, alpha, beta, st);
             break;
         case FOTCI_MODE_F32:
-        case FOTCI_MODE_BF16X3:
             run<float>(h, o, pivot, (char *)work, evals, resid, evecs, alpha, beta, st);
             break;
         default:

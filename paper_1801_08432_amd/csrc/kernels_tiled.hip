@@ -377,7 +377,8 @@ inline int pick_tile(int max_len, int elem) {
 }
 
 template <typename T>
-void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_t st) {
+void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_t st, void **ev) {
+    if (ev) hip_check(hipEventRecord((hipEvent_t)ev[0], st), "event");
     const int rt = pick_tile(t.max_nn, sizeof(T));
     const size_t lds_nn = (size_t)rt * t.max_nn * sizeof(T);
     switch (rt) {
@@ -386,6 +387,7 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
         case 2: hipLaunchKernelGGL((k_nn_diag<T, 2>), dim3(t.n_rtiles), dim3(kT), lds_nn, st, d, t, x, y); break;
         default: hipLaunchKernelGGL((k_nn_diag<T, 1>), dim3(t.n_rtiles), dim3(kT), lds_nn, st, d, t, x, y); break;
     }
+    if (ev) hip_check(hipEventRecord((hipEvent_t)ev[1], st), "event");
     const int ct = pick_tile(t.max_np, sizeof(T));
     const size_t lds_pp = (size_t)ct * t.max_np * sizeof(T);
     switch (ct) {
@@ -394,8 +396,10 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
         case 2: hipLaunchKernelGGL((k_pp<T, 2>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
         default: hipLaunchKernelGGL((k_pp<T, 1>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
     }
+    if (ev) hip_check(hipEventRecord((hipEvent_t)ev[2], st), "event");
     const size_t lds_pn = (size_t)t.max_nn * sizeof(T);
     hipLaunchKernelGGL(k_pn<T>, dim3(d.p.n_sd), dim3(kT), lds_pn, st, d, t, x, y);
+    if (ev) hip_check(hipEventRecord((hipEvent_t)ev[3], st), "event");
 }
 
 }  // namespace
@@ -411,14 +415,15 @@ void launch_materialize_tiled(const DevHam &d, const DevTiled &t, void *stream) 
     hip_check(hipGetLastError(), "materialize launch");
 }
 
-void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream) {
+void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream,
+                        void **events) {
     hipStream_t st = (hipStream_t)stream;
     if (d.p.n_sd == 0) return;
     if (!t.ok) fail(FOTCI_EINVAL, "basis too large for the tiled kernels (use FOTCI_MODE_F64_PLAIN)");
     if (mode == FOTCI_MODE_F64)
-        launch_all<double>(d, t, (const double *)x, (double *)y, st);
+        launch_all<double>(d, t, (const double *)x, (double *)y, st, events);
     else
-        launch_all<float>(d, t, (const float *)x, (float *)y, st);
+        launch_all<float>(d, t, (const float *)x, (float *)y, st, events);
     hip_check(hipGetLastError(), "apply launch");
 }
 

@@ -18,8 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfotci.so")
 MODE_F64_PLAIN = 0
 MODE_F64 = 1
 MODE_F32 = 2
-MODE_BF16X3 = 3
-MODES = {"f64_plain": MODE_F64_PLAIN, "f64": MODE_F64, "f32": MODE_F32, "bf16x3": MODE_BF16X3}
+MODES = {"f64_plain": MODE_F64_PLAIN, "f64": MODE_F64, "f32": MODE_F32}
 
 JUMP_PP2, JUMP_NN2, JUMP_P1, JUMP_N1 = 0, 1, 2, 3
 
@@ -28,7 +27,8 @@ EXPORTED = [
     "fotci_basis_export", "fotci_build_jumps", "fotci_free_jumps", "fotci_jumps_count", "fotci_jumps_export",
     "fotci_set_interaction", "fotci_free_ham", "fotci_ham_set_values", "fotci_ham_workspace_bytes",
     "fotci_ham_upload", "fotci_apply_H", "fotci_apply_H_vjp", "fotci_lanczos_workspace_bytes",
-    "fotci_lanczos_lowest", "fotci_ham_op_counts", "fotci_tridiag_eigh",
+    "fotci_lanczos_lowest", "fotci_ham_op_counts", "fotci_tridiag_eigh", "fotci_profile_start",
+    "fotci_profile_stop",
 ]
 
 
@@ -77,6 +77,8 @@ def lib():
         "fotci_lanczos_lowest": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P, P]),
         "fotci_ham_op_counts": (ctypes.c_int, [P, P, P, P, P]),
         "fotci_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
+        "fotci_profile_start": (ctypes.c_int, [P, I32]),
+        "fotci_profile_stop": (ctypes.c_int, [P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(l, name)
@@ -283,6 +285,18 @@ class Hamiltonian:
         if want_vectors:
             out["evecs"] = evecs
         return out
+
+    def profile_start(self, max_calls):
+        """Record HIP events around each apply_H kernel for up to max_calls calls."""
+        _check(lib().fotci_profile_start(self._h, int(max_calls)))
+
+    def profile_stop(self):
+        """Mean milliseconds per kernel over the recorded calls: dict name -> ms."""
+        ms = (ctypes.c_double * 4)()
+        names = (ctypes.c_char_p * 4)()
+        nk, nc = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fotci_profile_stop(self._h, ms, names, ctypes.byref(nk), ctypes.byref(nc)))
+        return {names[k].decode(): ms[k] for k in range(nk.value)}, nc.value
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
