@@ -82,35 +82,112 @@ __global__ __launch_bounds__(kThreads) void k_three_term(const T *__restrict__ y
     }
 }
 
-// partial[j*nb + block] = sum over the block's rows of V_j[r] * w[r], j < k.
-// Each thread keeps its rows of w in registers; each wave reduces with
-// shuffles, and the waves' sums meet in LDS once per block.
+// Tall-skinny kernels over the stored basis V (k vectors of n rows, leading
+// dimension ld, a multiple of 64 elements so every vector starts 256-byte
+// aligned). A block owns kChunk consecutive rows; each thread owns
+// kRowsPerThread of them, read as 16-byte vectors so that one load
+// instruction of a wave covers 1 KiB of contiguous rows. Loops over the basis
+// vectors are unrolled by kJU, so each thread has the loads of kJU vectors in
+// flight at once. The last block of the rows takes a guarded scalar path.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_multidot(const T *__restrict__ V, int64_t ld, int k,
-                                                       const double *__restrict__ w, int64_t n,
-                                                       double *__restrict__ partial) {
-    __shared__ double lds[kWaves][256];
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+
+constexpr int kJU = 4;
+
+template <typename T>
+__device__ __forceinline__ int64_t row_of(int64_t r0, int q, int e) {
+    constexpr int NV = Vec16<T>::n;
+    return r0 + (int64_t)q * kThreads * NV + (int64_t)threadIdx.x * NV + e;
+}
+
+// Rows of basis vector `v` owned by this thread, widened to float64 (0 past n).
+template <typename T, bool FULL>
+__device__ __forceinline__ void load_rows(const T *__restrict__ v, int64_t r0, int64_t n, double (&out)[kRowsPerThread]) {
+    using VT = typename Vec16<T>::type;
+    constexpr int NV = Vec16<T>::n;
+    constexpr int NL = kRowsPerThread / NV;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        if (FULL) {
+            const VT t = *(const VT *)(v + row_of<T>(r0, q, 0));
+            const T *tp = (const T *)&t;
+#pragma unroll
+            for (int e = 0; e < NV; ++e) out[q * NV + e] = (double)tp[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < NV; ++e) {
+                const int64_t r = row_of<T>(r0, q, e);
+                out[q * NV + e] = r < n ? (double)v[r] : 0.0;
+            }
+        }
+    }
+}
+
+// The same rows (the mapping of basis type T) of the float64 vector w.
+template <typename T, bool FULL>
+__device__ __forceinline__ void load_w(const double *__restrict__ w, int64_t r0, int64_t n,
+                                       double (&out)[kRowsPerThread]) {
+    constexpr int NV = Vec16<T>::n;
+    constexpr int NL = kRowsPerThread / NV;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        if (FULL) {
+#pragma unroll
+            for (int e = 0; e < NV; e += 2) {
+                const double2 t = *(const double2 *)(w + row_of<T>(r0, q, e));
+                out[q * NV + e] = t.x;
+                out[q * NV + e + 1] = t.y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < NV; ++e) {
+                const int64_t r = row_of<T>(r0, q, e);
+                out[q * NV + e] = r < n ? w[r] : 0.0;
+            }
+        }
+    }
+}
+
+// partial[j*nb + block] = sum over the block's rows of V_j[r] * w[r], j < k.
+// Each wave reduces with shuffles; the waves' sums meet in LDS once per 256
+// basis vectors.
+template <typename T, bool FULL>
+__device__ __forceinline__ void multidot_body(const T *__restrict__ V, int64_t ld, int k, const double *__restrict__ w,
+                                              int64_t n, double *__restrict__ partial, double (*lds)[256]) {
     const int64_t r0 = (int64_t)blockIdx.x * kChunk;
     const int nb = gridDim.x;
     double wr[kRowsPerThread];
-#pragma unroll
-    for (int e = 0; e < kRowsPerThread; ++e) {
-        const int64_t r = r0 + e * kThreads + threadIdx.x;
-        wr[e] = r < n ? w[r] : 0.0;
-    }
+    load_w<T, FULL>(w, r0, n, wr);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int j0 = 0; j0 < k; j0 += 256) {
         const int jn = min(256, k - j0);
-        for (int jj = 0; jj < jn; ++jj) {
-            const T *vj = V + (int64_t)(j0 + jj) * ld;
-            double acc = 0.0;
+        for (int jj = 0; jj < jn; jj += kJU) {
+            double acc[kJU];
+            double vr[kJU][kRowsPerThread];
 #pragma unroll
-            for (int e = 0; e < kRowsPerThread; ++e) {
-                const int64_t r = r0 + e * kThreads + threadIdx.x;
-                if (r < n) acc += (double)vj[r] * wr[e];
+            for (int u = 0; u < kJU; ++u)   // past the last vector: reload it, the sum is not stored
+                load_rows<T, FULL>(V + (int64_t)min(j0 + jj + u, k - 1) * ld, r0, n, vr[u]);
+#pragma unroll
+            for (int u = 0; u < kJU; ++u) {
+                acc[u] = 0.0;
+#pragma unroll
+                for (int e = 0; e < kRowsPerThread; ++e) acc[u] += vr[u][e] * wr[e];
             }
-            acc = wave_sum(acc);
-            if (lane == 0) lds[wid][jj] = acc;
+#pragma unroll
+            for (int u = 0; u < kJU; ++u) {
+                const double t = wave_sum(acc[u]);
+                if (lane == 0 && jj + u < jn) lds[wid][jj + u] = t;
+            }
         }
         __syncthreads();
         for (int jj = threadIdx.x; jj < jn; jj += kThreads) {
@@ -120,6 +197,17 @@ __global__ __launch_bounds__(kThreads) void k_multidot(const T *__restrict__ V, 
         }
         __syncthreads();
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multidot(const T *__restrict__ V, int64_t ld, int k,
+                                                       const double *__restrict__ w, int64_t n,
+                                                       double *__restrict__ partial) {
+    __shared__ double lds[kWaves][256];
+    if ((int64_t)(blockIdx.x + 1) * kChunk <= n)
+        multidot_body<T, true>(V, ld, k, w, n, partial, lds);
+    else
+        multidot_body<T, false>(V, ld, k, w, n, partial, lds);
 }
 
 // c[j] = sum_b partial[j*nb + b]; one block per j.
@@ -133,32 +221,69 @@ __global__ __launch_bounds__(kThreads) void k_reduce_rows(const double *__restri
     if (threadIdx.x == 0) c[j] = acc;
 }
 
-// w[r] -= sum_j c[j] V_j[r]
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_subtract(const T *__restrict__ V, int64_t ld, int k,
-                                                       const double *__restrict__ c, double *__restrict__ w,
-                                                       int64_t n) {
-    __shared__ double cs[kMaxIter];
-    for (int j = threadIdx.x; j < k; j += kThreads) cs[j] = c[j];
-    __syncthreads();
+// w[r] -= sum_j c[j] V_j[r]; with sq_partial, also the block's sum of the
+// updated w[r]^2 (the norm that follows the last pass).
+template <typename T, bool FULL>
+__device__ __forceinline__ void subtract_body(const T *__restrict__ V, int64_t ld, int k, const double *cs,
+                                              double *__restrict__ w, int64_t n, double *__restrict__ sq_partial,
+                                              double *lds) {
     const int64_t r0 = (int64_t)blockIdx.x * kChunk;
     double acc[kRowsPerThread];
 #pragma unroll
     for (int e = 0; e < kRowsPerThread; ++e) acc[e] = 0.0;
-    for (int j = 0; j < k; ++j) {
-        const T *vj = V + (int64_t)j * ld;
-        const double cj = cs[j];
+    int j = 0;
+    for (; j + kJU <= k; j += kJU) {
+        double vr[kJU][kRowsPerThread];
 #pragma unroll
-        for (int e = 0; e < kRowsPerThread; ++e) {
-            const int64_t r = r0 + e * kThreads + threadIdx.x;
-            if (r < n) acc[e] += cj * (double)vj[r];
+        for (int u = 0; u < kJU; ++u) load_rows<T, FULL>(V + (int64_t)(j + u) * ld, r0, n, vr[u]);
+#pragma unroll
+        for (int u = 0; u < kJU; ++u) {
+            const double cj = cs[j + u];
+#pragma unroll
+            for (int e = 0; e < kRowsPerThread; ++e) acc[e] += cj * vr[u][e];
         }
     }
+    for (; j < k; ++j) {
+        double vr[kRowsPerThread];
+        load_rows<T, FULL>(V + (int64_t)j * ld, r0, n, vr);
+        const double cj = cs[j];
 #pragma unroll
-    for (int e = 0; e < kRowsPerThread; ++e) {
-        const int64_t r = r0 + e * kThreads + threadIdx.x;
-        if (r < n) w[r] -= acc[e];
+        for (int e = 0; e < kRowsPerThread; ++e) acc[e] += cj * vr[e];
     }
+    double wr[kRowsPerThread];
+    load_w<T, FULL>(w, r0, n, wr);
+    double sq = 0.0;
+    constexpr int NV = Vec16<T>::n;
+    constexpr int NL = kRowsPerThread / NV;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const int64_t r = row_of<T>(r0, q, e);
+            const double t = wr[q * NV + e] - acc[q * NV + e];
+            if (FULL || r < n) {
+                w[r] = t;
+                sq += t * t;
+            }
+        }
+    }
+    if (sq_partial) {
+        sq = block_sum(sq, lds);
+        if (threadIdx.x == 0) sq_partial[blockIdx.x] = sq;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_subtract(const T *__restrict__ V, int64_t ld, int k,
+                                                       const double *__restrict__ c, double *__restrict__ w,
+                                                       int64_t n, double *__restrict__ sq_partial) {
+    extern __shared__ double cs[];   // k coefficients, then kWaves reduction slots
+    for (int j = threadIdx.x; j < k; j += kThreads) cs[j] = c[j];
+    __syncthreads();
+    if ((int64_t)(blockIdx.x + 1) * kChunk <= n)
+        subtract_body<T, true>(V, ld, k, cs, w, n, sq_partial, cs + k);
+    else
+        subtract_body<T, false>(V, ld, k, cs, w, n, sq_partial, cs + k);
 }
 
 // out = (T)(in * scale) with scale = 1 / *denom
@@ -210,6 +335,7 @@ int chunk_blocks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 struct Layout {
+    int64_t ld;   // basis leading dimension (elements): dim rounded up to 64
     int64_t basis, y, w, partial, scal, coef, S, ritz, hy, total;
 };
 
@@ -217,9 +343,10 @@ Layout make_layout(const fotci_ham *h, const fotci_lanczos_opts *o) {
     const int64_t dim = h->j->b->dim;
     const int es = (o->mode == FOTCI_MODE_F64 || o->mode == FOTCI_MODE_F64_PLAIN) ? 8 : 4;
     Layout L{};
+    L.ld = (dim + 63) & ~(int64_t)63;
     int64_t off = 0;
     L.basis = off;
-    off = a256(off + (int64_t)o->n_iter * dim * es);
+    off = a256(off + (int64_t)o->n_iter * L.ld * es);
     L.y = off;
     off = a256(off + dim * es);
     L.w = off;
@@ -255,6 +382,7 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
     double *Sd = (double *)(work + L.S);
     double *ritz = evecs ? evecs : (double *)(work + L.ritz);
     double *hy = (double *)(work + L.hy);
+    const int64_t ld = L.ld;
     const int sb = stream_blocks(dim);
     const int cb = chunk_blocks(dim);
     const int mode = o->mode;
@@ -275,20 +403,22 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
     double tnorm = 0.0;
     int k = 0;
     for (int i = 0; i < o->n_iter; ++i) {
-        T *vi = basis + (int64_t)i * dim;
+        T *vi = basis + (int64_t)i * ld;
         launch_apply(h, mode, vi, y, st);
         dot_into((const T *)vi, (const T *)y, scal + 0, 0);
         hipLaunchKernelGGL(k_three_term<T>, dim3(sb), dim3(kThreads), 0, st, (const T *)y, (const T *)vi,
-                           (const T *)(i > 0 ? vi - dim : nullptr), (const double *)(scal + 0),
+                           (const T *)(i > 0 ? vi - ld : nullptr), (const double *)(scal + 0),
                            (const double *)(scal + 1), w, dim);
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_multidot<T>, dim3(cb), dim3(kThreads), 0, st, (const T *)basis, dim, i + 1,
+            hipLaunchKernelGGL(k_multidot<T>, dim3(cb), dim3(kThreads), 0, st, (const T *)basis, ld, i + 1,
                                (const double *)w, dim, partial);
             hipLaunchKernelGGL(k_reduce_rows, dim3(i + 1), dim3(kThreads), 0, st, (const double *)partial, cb, coef);
-            hipLaunchKernelGGL(k_subtract<T>, dim3(cb), dim3(kThreads), 0, st, (const T *)basis, dim, i + 1,
-                               (const double *)coef, w, dim);
+            // the second pass also leaves the block sums of ||w||^2 in partial
+            hipLaunchKernelGGL(k_subtract<T>, dim3(cb), dim3(kThreads), (size_t)(i + 1 + kWaves) * 8, st,
+                               (const T *)basis, ld, i + 1, (const double *)coef, w, dim,
+                               pass == 1 ? partial : (double *)nullptr);
         }
-        dot_into((const double *)w, (const double *)w, scal + 1, 1);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, cb, scal + 1, 1);
         hip_check(hipGetLastError(), "lanczos launch");
         double ab[2];
         hip_check(hipMemcpyAsync(ab, scal, 16, hipMemcpyDeviceToHost, st), "lanczos copy");
@@ -303,7 +433,7 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
         be.push_back(ab[1]);
         if (!(ab[1] > 1e-12 * tnorm)) break;   // invariant subspace reached
         hipLaunchKernelGGL(k_scale_store<T>, dim3(sb), dim3(kThreads), 0, st, (const double *)w,
-                           (const double *)(scal + 1), basis + (int64_t)(i + 1) * dim, dim);
+                           (const double *)(scal + 1), basis + (int64_t)(i + 1) * ld, dim);
     }
     if (alpha_out)
         for (int i = 0; i < o->n_iter; ++i) alpha_out[i] = i < k ? al[i] : 0.0;
@@ -320,7 +450,7 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
         for (int j = 0; j < nk; ++j) S[(size_t)l * nk + j] = z[(size_t)l * k + j];
     hip_check(hipMemcpyAsync(Sd, S.data(), S.size() * 8, hipMemcpyHostToDevice, st), "ritz copy");
     hipLaunchKernelGGL(k_ritz<T>, dim3((int)((dim + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
-                       (const T *)basis, dim, k, (const double *)Sd, nk, ritz, dim);
+                       (const T *)basis, ld, k, (const double *)Sd, nk, ritz, dim);
     for (int j = 0; j < nk; ++j) {
         double *yj = ritz + (int64_t)j * dim;
         // normalise the Ritz vector in float64

@@ -121,10 +121,10 @@ def test_eigenvalue_gradient_matches_oracle_hellmann_feynman():
         assert np.allclose(got, ref[kk], atol=1e-8), kk
 
 
-def test_eigenvalue_gradient_pf_4p4n_fd_and_euler():
+@pytest.fixture(scope="module")
+def pf_grad():
     """The 4p4n pf-shell gradient workload: L = sum_k w_k E_k over the lowest
-    5, w ~ U(0,1); adjoint densities against central differences on 64
-    random independent elements, and the Euler identity."""
+    5, w ~ U(0,1); gradients from the adjoint densities."""
     w = inputs.workload("pf_4p4n_grad")
     rng = w["rng"]
     wk = rng.uniform(0, 1, 5)
@@ -137,25 +137,42 @@ def test_eigenvalue_gradient_pf_4p4n_fd_and_euler():
     L.backward()
     grads = {k: t.grad.numpy() for k, t in zip(KEYS, theta)}
     _say("[grad] E", E.detach().cpu().numpy())
-    # Euler identity: H is linear in theta
-    euler = sum(float(np.sum(grads[k] * np.asarray(w[k]))) for k in KEYS)
-    _say("[grad] Euler identity: sum theta dL/dtheta = %.12f, L = %.12f" % (euler, float(L)))
-    assert abs(euler - float(L)) <= 1e-9 * abs(float(L))
     o = ob.build_basis(w["two_j"], w["Z"], w["N"], w["two_M"])
+    elements = _independent_elements(w, o.ms, rng, 64)
+    yield dict(w=w, wk=wk, ham=ham, piv=piv, n_iter=n_iter, L=float(L.detach()), grads=grads,
+               elements=elements)
+    ham.set_values(w)
+
+
+def test_eigenvalue_gradient_pf_4p4n_euler(pf_grad):
+    """Euler identity: H is linear in theta, so sum theta dL/dtheta = L."""
+    w, grads, L = pf_grad["w"], pf_grad["grads"], pf_grad["L"]
+    euler = sum(float(np.sum(grads[k] * np.asarray(w[k]))) for k in KEYS)
+    _say("[grad] Euler identity: sum theta dL/dtheta = %.12f, L = %.12f" % (euler, L))
+    assert abs(euler - L) <= 1e-9 * abs(L)
+
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_eigenvalue_gradient_pf_4p4n_fd(pf_grad, chunk):
+    """Adjoint densities against central differences (h = 1e-4 MeV) of the
+    float64 Lanczos eigenvalues, on 64 random independent elements (16 per
+    chunk)."""
+    import time
+    w, wk, ham, piv = pf_grad["w"], pf_grad["wk"], pf_grad["ham"], pf_grad["piv"]
     h = 1e-4
     worst = 0.0
-    import time
-    for i, (kind, r, c) in enumerate(_independent_elements(w, o.ms, rng, 64)):
+    for i in range(16 * chunk, 16 * chunk + 16):
+        kind, r, c = pf_grad["elements"][i]
         t0 = time.time()
         vals = []
         for sgn in (1.0, -1.0):
             ham.set_values(_perturbed(w, kind, r, c, sgn * h))
-            ev = ham.lanczos_lowest(piv, 5, n_iter, mode="f64")["evals"]
+            ev = ham.lanczos_lowest(piv, 5, pf_grad["n_iter"], mode="f64")["evals"]
             vals.append(float(np.dot(wk, ev)))
+        ham.set_values(w)
         fd = (vals[0] - vals[1]) / (2 * h)
-        ad = _indep_grad(grads, kind, r, c)
+        ad = _indep_grad(pf_grad["grads"], kind, r, c)
         worst = max(worst, abs(fd - ad) / (1e-6 + 1e-4 * abs(ad)))
         _say("[grad] %2d %s[%d,%d] fd %.9f adjoint %.9f (%.1f s)" % (i, kind, r, c, fd, ad, time.time() - t0))
         assert abs(fd - ad) <= 1e-6 + 1e-4 * abs(ad), (kind, r, c, fd, ad)
     _say("[grad] worst FD ratio to tolerance", worst)
-    ham.set_values(w)
