@@ -163,6 +163,7 @@ struct DevTiled {
     const int32_t *pn_ptr;       // [(n_sectors*nq)*n_t16 + 1]
     const uint32_t *pn_code;     // (dst col << 11) | (B << 5) | (src col - tile start) << 1 | (phase < 0);
                                  // kNullCode pads rounds of 64 entries with distinct destinations
+    int64_t n_pn_code;           // entries of pn_code
     int32_t n_t16;               // tiles per sector slot (ceil(max nn / 16))
     int32_t kp_pad;              // max proton one-body jumps into a row per class, rounded up to 4
     int32_t max_nn, max_np;

@@ -213,7 +213,8 @@ void build_tiled_tables(fotci_ham *h) {
         }
     }
     t.pn_ptr[cnt.size() - 1] = (int64_t)t.pn_code.size();
-    if ((int64_t)t.pn_code.size() > INT32_MAX) ok = false;
+    // the pn kernel reads the codes through a buffer resource with 32-bit byte offsets
+    if ((int64_t)t.pn_code.size() * 4 > INT32_MAX) ok = false;
     t.ok = ok;
     const int npsd = (int)b->p.sd.size();
     t.order.resize(npsd);
@@ -379,6 +380,7 @@ std::vector<Item> items(fotci_ham *h) {
     dt.rt_rows = 8;
     dt.ct_cols = 8;
     dt.n_t16 = std::max(tt.n_t16, 1);
+    dt.n_pn_code = (int64_t)tt.pn_code.size();
     dt.kp_pad = tt.kp_pad;
     dt.max_nn = tt.max_nn;
     dt.max_np = tt.max_np;

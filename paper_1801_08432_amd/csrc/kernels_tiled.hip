@@ -215,97 +215,186 @@ __device__ __forceinline__ double signed_by(double v, uint32_t code) {
 
 constexpr int kKP = 32;   // max proton one-body jumps into one row per class
 
-// LDS strides chosen so that the matrix-core operand reads (16 rows of C
-// per k-slot) and the R tile stores hit distinct banks in each half-wave.
+// LDS layouts of the per-wave tile R[B][col] (B < 64 neutron labels, col < 16
+// source columns) and the stride of C[B][k]. float: R is stored column-major
+// with a column stride of 68 words, so a lane's four accumulator rows (4
+// consecutive B) leave in one 16-byte store and 8 lanes of a store cover all
+// 32 banks. double: the accumulator rows of a lane are 4 apart, R is
+// row-major with stride 16.
 template <typename T>
 struct Lds;
 template <>
 struct Lds<float> {
     static constexpr int c_stride = 34;   // 2*col + k spans all 32 banks
-    static constexpr int r_stride = 20;   // rows 4 apart land 16 banks apart
+    static constexpr int r_words = 16 * 68;
+    static __device__ __forceinline__ void store(float *R, int lane, int bt, const floatx4 &acc) {
+        *(floatx4 *)(R + (lane & 15) * 68 + 16 * bt + 4 * (lane >> 4)) = acc;
+    }
+    static __device__ __forceinline__ float at(const float *R, uint32_t B, uint32_t col) { return R[col * 68 + B]; }
 };
 template <>
 struct Lds<double> {
     static constexpr int c_stride = 33;
-    static constexpr int r_stride = 16;
+    static constexpr int r_words = 64 * 16;
+    static __device__ __forceinline__ void store(double *R, int lane, int bt, const doublex4 &acc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[(16 * bt + Mma<double>::row(lane, r)) * 16 + (lane & 15)] = acc[r];
+    }
+    static __device__ __forceinline__ double at(const double *R, uint32_t B, uint32_t col) { return R[B * 16 + col]; }
 };
+
+__device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0);
+}
+
+// The loads of one 16-column source tile: KST x values per lane and the first
+// 256 gather codes. Their number is fixed and no lane skips them (buffer
+// loads past a range return 0), so the compiler can count them and let the
+// next tile's loads stay in flight while the current tile is worked on.
+template <typename T, int KST>
+struct PnTile {
+    T xv[KST];
+    uint32_t cr[4];
+    int e0, e1;
+};
+
+// Gather-list ranges of the wave's tiles t = wid + W*(j0 + lane), one tile
+// per lane (ends past the last tile clamp to it), read once per 64 tiles so
+// that the tile loop picks them with readlane and issues no dependent load.
+struct PnBounds {
+    int b0, b1;
+};
+
+__device__ __forceinline__ void pn_bounds(PnBounds &pb, int j0, int wid, int ntiles, const int32_t *__restrict__ pnp,
+                                          int lane) {
+    const int tt = wid + (kT / 64) * (j0 + lane);
+    pb.b0 = pnp[min(tt, ntiles)];
+    pb.b1 = pnp[min(tt + 1, ntiles)];
+}
+
+// Tile j of the wave (t = wid + W*j); past the last tile it reloads that tile
+// and is marked empty.
+template <typename T, int KST>
+__device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int ntiles, PnBounds &pb,
+                                         const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+                                         const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int lane) {
+    if (j > 0 && (j & 63) == 0) pn_bounds(pb, j, wid, ntiles, pnp, lane);   // uniform, every 64 tiles
+    const int tt = wid + (kT / 64) * j;
+    const int tc = min(tt, ntiles - 1);
+    b.e0 = __builtin_amdgcn_readlane(pb.b0, j & 63);
+    b.e1 = tt < ntiles ? __builtin_amdgcn_readlane(pb.b1, j & 63) : b.e0;
+    const unsigned soff = (unsigned)(16 * tc) * (unsigned)sizeof(T);
+#pragma unroll
+    for (int ks = 0; ks < KST; ++ks) b.xv[ks] = buffer_load<T>(xr, voff[ks], soff);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
+}
+
+// One gather entry: yl[dst] += phase * R[B][src] (code layout as in pn_code).
+template <typename T, bool PRIV>
+__device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__ R, uint32_t c) {
+    const T v = signed_by(Lds<T>::at(R, (c >> 5) & 63u, (c >> 1) & 15u), c);
+    if (PRIV)
+        yl[c >> 11] += v;
+    else
+        atomicAdd(&yl[c >> 11], v);
+}
+
+// Contraction and gather of one fetched tile; cv holds the class's C operand.
+// PRIV: yl is this wave's private output row, updated by plain LDS
+// read-modify-write (the lanes of one round have distinct destinations and a
+// wave's LDS operations complete in order); otherwise yl is the workgroup's
+// shared row, updated with LDS atomics.
+template <typename T, bool PRIV, int NBT, int KST>
+__device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[NBT][KST],
+                                        __amdgpu_buffer_rsrc_t cres, int lane, T *__restrict__ R,
+                                        T *__restrict__ yl) {
+    typedef typename Mma<T>::acc_t acc_t;
+    if (b.e0 == b.e1) return;   // uniform: no neutron jump leaves this tile
+    acc_t acc[NBT];
+#pragma unroll
+    for (int bt = 0; bt < NBT; ++bt) acc[bt] = Mma<T>::zero();
+#pragma unroll
+    for (int ks = 0; ks < KST; ++ks)
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) acc[bt] = Mma<T>::mma(cv[bt][ks], b.xv[ks], acc[bt]);
+#pragma unroll
+    for (int bt = 0; bt < NBT; ++bt) Lds<T>::store(R, lane, bt, acc[bt]);
+    // a wave's LDS operations complete in issue order: the gather below
+    // sees the stores above without a workgroup barrier
+    __builtin_amdgcn_wave_barrier();
+    // code bits 5..10: neutron label B (row of R), bits 1..4: source column in
+    // the tile. Each round of 64 entries has distinct destinations (null codes
+    // pad it), so the lanes of one LDS atomic never hit the same address.
+    const int ne = b.e1 - b.e0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t c = b.cr[i];
+        if (lane + 64 * i < ne && c != kNullCode) pn_add<T, PRIV>(yl, R, c);
+    }
+    for (int i = lane + 256; i < ne; i += 64) {
+        const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i) * 4u);
+        if (c != kNullCode) pn_add<T, PRIV>(yl, R, c);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
 
 // One wave's tiles of one class, specialised on the number of 16-row tiles
 // of neutron labels (NBT) and of 4-jump k-steps (KST) so the inner loop has
-// no runtime guards around the matrix-core instructions.
-template <typename T, int NBT, int KST>
+// no runtime guards around the matrix-core instructions. Two register sets
+// alternate: the loads of the wave's next tile are issued before the current
+// tile's contraction and gather.
+template <typename T, bool PRIV, int NBT, int KST>
 __device__ __forceinline__ void pn_tiles(const T *__restrict__ Cl, const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
-                                         const int32_t *__restrict__ pnp, const uint32_t *__restrict__ pnc, int ntiles,
-                                         int wid, int lane, int col_l, T *__restrict__ R, T *__restrict__ yl) {
-    typedef typename Mma<T>::acc_t acc_t;
-    for (int t = wid; t < ntiles; t += kT / 64) {
-        const int e0 = __builtin_amdgcn_readfirstlane(pnp[t]);
-        const int e1 = __builtin_amdgcn_readfirstlane(pnp[t + 1]);
-        if (e0 == e1) continue;
-        const unsigned soff = (unsigned)(16 * t) * (unsigned)sizeof(T);
-        T xv[KST];
+                                         const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
+                                         int wid, int lane, T *__restrict__ R, T *__restrict__ yl) {
+    constexpr int CS = Lds<T>::c_stride;
+    if (wid >= ntiles) return;
+    T cv[NBT][KST];   // the class's C operand stays in registers for all tiles
 #pragma unroll
-        for (int ks = 0; ks < KST; ++ks) xv[ks] = buffer_load<T>(xr, voff[ks], soff);
-        const int ne = e1 - e0;
-        const uint32_t *codes = pnc + e0;
-        uint32_t cr[4];
+    for (int bt = 0; bt < NBT; ++bt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) cr[i] = lane + 64 * i < ne ? codes[lane + 64 * i] : 0u;
-        acc_t acc[NBT];
-#pragma unroll
-        for (int b = 0; b < NBT; ++b) acc[b] = Mma<T>::zero();
-        constexpr int CS = Lds<T>::c_stride, RS = Lds<T>::r_stride;
-#pragma unroll
-        for (int ks = 0; ks < KST; ++ks)
-#pragma unroll
-            for (int bt = 0; bt < NBT; ++bt) acc[bt] = Mma<T>::mma(Cl[bt * 16 * CS + 4 * ks], xv[ks], acc[bt]);
-#pragma unroll
-        for (int bt = 0; bt < NBT; ++bt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) R[(16 * bt + Mma<T>::row(lane, r)) * RS + col_l] = acc[bt][r];
-        // a wave's LDS operations complete in issue order: the gather below
-        // sees the stores above without a workgroup barrier
-        __builtin_amdgcn_wave_barrier();
-        // code bits 5..10: neutron label B (row of R), bits 1..4: source column in the tile
-        // each round of 64 entries has distinct destinations (null codes pad
-        // it), so the lanes of one LDS atomic never hit the same address
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (lane + 64 * i < ne && cr[i] != kNullCode)
-                atomicAdd(&yl[cr[i] >> 11], signed_by(R[((cr[i] >> 5) & 63u) * RS + ((cr[i] >> 1) & 15u)], cr[i]));
-        for (int i = lane + 256; i < ne; i += 64) {
-            const uint32_t code = codes[i];
-            if (code != kNullCode)
-                atomicAdd(&yl[code >> 11], signed_by(R[((code >> 5) & 63u) * RS + ((code >> 1) & 15u)], code));
-        }
-        __builtin_amdgcn_wave_barrier();
+        for (int ks = 0; ks < KST; ++ks) cv[bt][ks] = Cl[bt * 16 * CS + 4 * ks];
+    PnBounds pb;
+    pn_bounds(pb, 0, wid, ntiles, pnp, lane);
+    PnTile<T, KST> A, B;
+    pn_fetch<T, KST>(A, 0, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+    for (int j = 0;; j += 2) {
+        pn_fetch<T, KST>(B, j + 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_work<T, PRIV, NBT, KST>(A, cv, cres, lane, R, yl);
+        if (wid + (kT / 64) * (j + 1) >= ntiles) break;
+        pn_fetch<T, KST>(A, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_work<T, PRIV, NBT, KST>(B, cv, cres, lane, R, yl);
+        if (wid + (kT / 64) * (j + 2) >= ntiles) break;
     }
 }
 
-template <typename T, int NBT>
+template <typename T, bool PRIV, int NBT>
 __device__ __forceinline__ void pn_tiles_k(int ksteps, const T *Cl, const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
-                                           const int32_t *pnp, const uint32_t *pnc, int ntiles, int wid, int lane,
-                                           int col_l, T *R, T *yl) {
+                                           const int32_t *pnp, __amdgpu_buffer_rsrc_t pnc, int ntiles, int wid,
+                                           int lane, T *R, T *yl) {
     switch (ksteps) {
-        case 1: pn_tiles<T, NBT, 1>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
-        case 2: pn_tiles<T, NBT, 2>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
-        case 3: pn_tiles<T, NBT, 3>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
-        case 4: pn_tiles<T, NBT, 4>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
-        case 5: pn_tiles<T, NBT, 5>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
-        case 6: pn_tiles<T, NBT, 6>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
-        case 7: pn_tiles<T, NBT, 7>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
-        default: pn_tiles<T, NBT, 8>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, col_l, R, yl); break;
+        case 1: pn_tiles<T, PRIV, NBT, 1>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 2: pn_tiles<T, PRIV, NBT, 2>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 3: pn_tiles<T, PRIV, NBT, 3>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 4: pn_tiles<T, PRIV, NBT, 4>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 5: pn_tiles<T, PRIV, NBT, 5>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 6: pn_tiles<T, PRIV, NBT, 6>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 7: pn_tiles<T, PRIV, NBT, 7>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        default: pn_tiles<T, PRIV, NBT, 8>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
     }
 }
 
-template <typename T>
+// PRIV: each wave accumulates into its own output row (kT/64 rows of max_nn
+// in dynamic LDS, summed at the end); otherwise one shared row with atomics.
+template <typename T, bool PRIV>
 __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
     constexpr int CS = Lds<T>::c_stride;
-    __shared__ T Rw[kT / 64][kNB * Lds<T>::r_stride];
+    __shared__ __align__(16) T Rw[kT / 64][Lds<T>::r_words];
     __shared__ T C[kNB * CS];
     __shared__ int32_t srcb[kKP];
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *yl = reinterpret_cast<T *>(smem_raw);   // output row [nn]
+    T *yall = reinterpret_cast<T *>(smem_raw);   // output row(s) [nn]
 
     const int ip = TT.order[blockIdx.x];
     const int tid = threadIdx.x;
@@ -320,8 +409,13 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
     const T *vq = TabT<T>::vq(P);
     const __amdgpu_buffer_rsrc_t xr =
         __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)sizeof(T)), kBufFlags);
+    const __amdgpu_buffer_rsrc_t cres =
+        __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn_code, (short)0, (int)(TT.n_pn_code * 4), kBufFlags);
     T *R = Rw[wid];
-    for (int c = tid; c < nn; c += kT) yl[c] = 0;
+    const int ystride = TT.max_nn;
+    T *yl = PRIV ? yall + wid * ystride : yall;
+    for (int w = 0; w < (PRIV ? kT / 64 : 1); ++w)
+        for (int c = tid; c < nn; c += kT) yall[w * ystride + c] = 0;
     bool any = false;
     for (int q = 0; q < nq; ++q) {
         const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q], a1 = P.p.ob_ptr[(int64_t)ip * nq + q + 1];
@@ -359,15 +453,21 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
         const T *Cl = C + col_l * CS + kq;
         const int32_t *pnp = TT.pn_ptr + pslot;
         switch (nbt) {
-            case 1: pn_tiles_k<T, 1>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
-            case 2: pn_tiles_k<T, 2>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
-            case 3: pn_tiles_k<T, 3>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
-            default: pn_tiles_k<T, 4>(ksteps, Cl, voff, xr, pnp, TT.pn_code, ntiles, wid, lane, col_l, R, yl); break;
+            case 1: pn_tiles_k<T, PRIV, 1>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 2: pn_tiles_k<T, PRIV, 2>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 3: pn_tiles_k<T, PRIV, 3>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            default: pn_tiles_k<T, PRIV, 4>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
         }
     }
     if (!any) return;
     __syncthreads();
-    for (int c = tid; c < nn; c += kT) y[base + c] += yl[c];
+    for (int c = tid; c < nn; c += kT) {
+        T v = yall[c];
+        if (PRIV)
+#pragma unroll
+            for (int w = 1; w < kT / 64; ++w) v += yall[w * ystride + c];
+        y[base + c] += v;
+    }
 }
 
 inline int pick_tile(int max_len, int elem) {
@@ -397,8 +497,16 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
         default: hipLaunchKernelGGL((k_pp<T, 1>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
     }
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[2], st), "event");
-    const size_t lds_pn = (size_t)t.max_nn * sizeof(T);
-    hipLaunchKernelGGL(k_pn<T>, dim3(d.p.n_sd), dim3(kT), lds_pn, st, d, t, x, y);
+    // float: wave-private output rows (plain LDS adds) when they fit; LDS
+    // float atomics are far slower than a read and a write
+    const size_t lds_priv = (size_t)(kT / 64) * t.max_nn * sizeof(T);
+    bool priv = false;
+    if constexpr (sizeof(T) == 4) {
+        priv = lds_priv <= 32768;
+        if (priv) hipLaunchKernelGGL((k_pn<T, true>), dim3(d.p.n_sd), dim3(kT), lds_priv, st, d, t, x, y);
+    }
+    if (!priv)
+        hipLaunchKernelGGL((k_pn<T, false>), dim3(d.p.n_sd), dim3(kT), (size_t)t.max_nn * sizeof(T), st, d, t, x, y);
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[3], st), "event");
 }
 
