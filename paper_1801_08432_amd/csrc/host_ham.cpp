@@ -86,7 +86,7 @@ void build_tiled_tables(fotci_ham *h) {
     const int nq = cl.nq;
     const int S = (int)b->sectors.size();
     HostTiled &t = h->tt;
-    constexpr int kTL = 16;    // source tile of the pn kernel
+    constexpr int kTL = kPnTile;   // source tile of the pn kernel
     bool ok = true;
     for (int q = 0; q < nq; ++q)
         if (cl.ops[q].size() > 64) ok = false;
@@ -150,7 +150,8 @@ void build_tiled_tables(fotci_ham *h) {
     for (size_t i = 0; i + 1 < h->tp.ob_ptr.size(); ++i) kpmax = std::max(kpmax, h->tp.ob_ptr[i + 1] - h->tp.ob_ptr[i]);
     t.kp_pad = (kpmax + 3) & ~3;
     // up to 32 proton jumps per class in the pn kernel; x addressed with 32-bit byte offsets
-    if (kpmax > 32 || b->dim * 8 >= ((int64_t)1 << 31) || t.max_nn >= (1 << 21)) ok = false;
+    // destination columns (and one padding column) in 20 bits of a gather code
+    if (kpmax > 32 || b->dim * 8 >= ((int64_t)1 << 31) || t.max_nn >= (1 << 20) - 1) ok = false;
     std::vector<int32_t> nsec_to_bsec(b->n.sectors.size(), -1);
     for (int s = 0; s < S; ++s) nsec_to_bsec[b->sectors[s].n_sector] = s;
     const auto &rec = h->j->rec[FOTCI_JUMP_N1];
@@ -176,9 +177,10 @@ void build_tiled_tables(fotci_ham *h) {
         for (size_t i : by_src) order[fill[slot(rec[i])]++] = i;
     }
     // Pack each slot into rounds of 64 entries with distinct destination
-    // columns (one round = one LDS atomic instruction of a wave, so no two
-    // lanes add to the same address); every round but the last is padded
-    // with null codes to 64 entries.
+    // columns (one round = one LDS instruction of a wave, so no two lanes add
+    // to the same address); every round is padded to 64 entries with the
+    // null code, which adds R element 0 to the padding column max_nn.
+    const uint32_t null_code = (uint32_t)t.max_nn << 11;
     t.pn_ptr.assign(cnt.size(), 0);
     t.pn_code.clear();
     std::vector<std::vector<uint32_t>> rounds;
@@ -192,8 +194,8 @@ void build_tiled_tables(fotci_ham *h) {
             const uint32_t dcol = (uint32_t)b->n.sd_local[r.dst];
             const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kTL);
             const uint32_t B = (uint32_t)cl.local_of[r.label];
-            // (destination column << 11) | (B << 5) | (source offset in the tile << 1) | sign
-            const uint32_t code = (dcol << 11) | ((B & 63u) << 5) | (so << 1) | (r.phase < 0 ? 1u : 0u);
+            // sign << 31 | destination column << 11 | R element (source offset in the tile, label B)
+            const uint32_t code = (r.phase < 0 ? 0x80000000u : 0u) | (dcol << 11) | (so * (uint32_t)kPnRStride + B);
             size_t g = 0;
             for (; g < rounds.size(); ++g) {
                 if (rounds[g].size() >= 64) continue;
@@ -208,8 +210,7 @@ void build_tiled_tables(fotci_ham *h) {
         }
         for (size_t g = 0; g < rounds.size(); ++g) {
             for (uint32_t c : rounds[g]) t.pn_code.push_back(c);
-            if (g + 1 < rounds.size())
-                for (size_t p = rounds[g].size(); p < 64; ++p) t.pn_code.push_back(kNullCode);
+            for (size_t p = rounds[g].size(); p < 64; ++p) t.pn_code.push_back(null_code);
         }
     }
     t.pn_ptr[cnt.size() - 1] = (int64_t)t.pn_code.size();
@@ -381,6 +382,7 @@ std::vector<Item> items(fotci_ham *h) {
     dt.ct_cols = 8;
     dt.n_t16 = std::max(tt.n_t16, 1);
     dt.n_pn_code = (int64_t)tt.pn_code.size();
+    dt.pn_null = (uint32_t)tt.max_nn << 11;
     dt.kp_pad = tt.kp_pad;
     dt.max_nn = tt.max_nn;
     dt.max_np = tt.max_np;

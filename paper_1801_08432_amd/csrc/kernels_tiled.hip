@@ -41,7 +41,6 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;      // threads per workgroup (4 waves)
 constexpr int kTile = 8;     // rows (nn kernel) / columns (pp kernel) per tile
-constexpr int kNB = 64;      // max neutron labels per class (rows of R)
 constexpr int kLdsTile = 65536;  // bytes of LDS for a staged tile
 
 template <typename T>
@@ -205,42 +204,34 @@ template <>
 __device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
-// flip the sign of v when the low bit of code is set
+// flip the sign of v when bit 31 of code is set
 __device__ __forceinline__ float signed_by(float v, uint32_t code) {
-    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ (code << 31));
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ (code & 0x80000000u));
 }
 __device__ __forceinline__ double signed_by(double v, uint32_t code) {
-    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)code << 63));
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)(code & 0x80000000u) << 32));
 }
 
-constexpr int kKP = 32;   // max proton one-body jumps into one row per class
 
-// LDS layouts of the per-wave tile R[B][col] (B < 64 neutron labels, col < 16
-// source columns) and the stride of C[B][k]. float: R is stored column-major
-// with a column stride of 68 words, so a lane's four accumulator rows (4
-// consecutive B) leave in one 16-byte store and 8 lanes of a store cover all
-// 32 banks. double: the accumulator rows of a lane are 4 apart, R is
-// row-major with stride 16.
+// LDS layout of the per-wave tile R[B][col] (B < 64 neutron labels, col < 16
+// source columns): column-major with column stride kPnRStride = 68 elements.
+// float: a lane's four accumulator rows (4 consecutive B) leave in one
+// 16-byte store, and 8 lanes of a store cover all 32 banks. double: the
+// accumulator rows of a lane are 4 apart and leave in four stores.
 template <typename T>
 struct Lds;
 template <>
 struct Lds<float> {
-    static constexpr int c_stride = 34;   // 2*col + k spans all 32 banks
-    static constexpr int r_words = 16 * 68;
     static __device__ __forceinline__ void store(float *R, int lane, int bt, const floatx4 &acc) {
-        *(floatx4 *)(R + (lane & 15) * 68 + 16 * bt + 4 * (lane >> 4)) = acc;
+        *(floatx4 *)(R + (lane & 15) * kPnRStride + 16 * bt + 4 * (lane >> 4)) = acc;
     }
-    static __device__ __forceinline__ float at(const float *R, uint32_t B, uint32_t col) { return R[col * 68 + B]; }
 };
 template <>
 struct Lds<double> {
-    static constexpr int c_stride = 33;
-    static constexpr int r_words = 64 * 16;
     static __device__ __forceinline__ void store(double *R, int lane, int bt, const doublex4 &acc) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) R[(16 * bt + Mma<double>::row(lane, r)) * 16 + (lane & 15)] = acc[r];
+        for (int r = 0; r < 4; ++r) R[(lane & 15) * kPnRStride + 16 * bt + Mma<double>::row(lane, r)] = acc[r];
     }
-    static __device__ __forceinline__ double at(const double *R, uint32_t B, uint32_t col) { return R[B * 16 + col]; }
 };
 
 __device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, unsigned voff) {
@@ -251,10 +242,12 @@ __device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, un
 // 256 gather codes. Their number is fixed and no lane skips them (buffer
 // loads past a range return 0), so the compiler can count them and let the
 // next tile's loads stay in flight while the current tile is worked on.
+constexpr int kPnRounds = 8;   // gather rounds of a tile loaded with its x values
+
 template <typename T, int KST>
 struct PnTile {
     T xv[KST];
-    uint32_t cr[4];
+    uint32_t cr[kPnRounds];
     int e0, e1;
 };
 
@@ -287,17 +280,19 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
 #pragma unroll
     for (int ks = 0; ks < KST; ++ks) b.xv[ks] = buffer_load<T>(xr, voff[ks], soff);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
+    for (int i = 0; i < kPnRounds; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
 }
 
-// One gather entry: yl[dst] += phase * R[B][src] (code layout as in pn_code).
+// One gather entry: yl[dst] += phase * R[element] (code layout as in
+// pn_code). With private rows the padding code is applied too (it adds to
+// the padding column); with the shared row it is skipped.
 template <typename T, bool PRIV>
-__device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__ R, uint32_t c) {
-    const T v = signed_by(Lds<T>::at(R, (c >> 5) & 63u, (c >> 1) & 15u), c);
+__device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__ R, uint32_t c, uint32_t null_code) {
+    const T v = signed_by(R[c & 0x7ffu], c);
     if (PRIV)
-        yl[c >> 11] += v;
-    else
-        atomicAdd(&yl[c >> 11], v);
+        yl[(c >> 11) & 0xfffffu] += v;
+    else if (c != null_code)
+        atomicAdd(&yl[(c >> 11) & 0xfffffu], v);
 }
 
 // Contraction and gather of one fetched tile; cv holds the class's C operand.
@@ -307,8 +302,8 @@ __device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__
 // shared row, updated with LDS atomics.
 template <typename T, bool PRIV, int NBT, int KST>
 __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[NBT][KST],
-                                        __amdgpu_buffer_rsrc_t cres, int lane, T *__restrict__ R,
-                                        T *__restrict__ yl) {
+                                        __amdgpu_buffer_rsrc_t cres, uint32_t null_code, int lane,
+                                        T *__restrict__ R, T *__restrict__ yl) {
     typedef typename Mma<T>::acc_t acc_t;
     if (b.e0 == b.e1) return;   // uniform: no neutron jump leaves this tile
     acc_t acc[NBT];
@@ -323,19 +318,15 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
     // a wave's LDS operations complete in issue order: the gather below
     // sees the stores above without a workgroup barrier
     __builtin_amdgcn_wave_barrier();
-    // code bits 5..10: neutron label B (row of R), bits 1..4: source column in
-    // the tile. Each round of 64 entries has distinct destinations (null codes
-    // pad it), so the lanes of one LDS atomic never hit the same address.
+    // Each round of 64 entries has distinct destinations, so the lanes of one
+    // LDS instruction never hit the same address; the list of a tile is a
+    // whole number of rounds, so rounds are skipped per wave, not per lane.
     const int ne = b.e1 - b.e0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t c = b.cr[i];
-        if (lane + 64 * i < ne && c != kNullCode) pn_add<T, PRIV>(yl, R, c);
-    }
-    for (int i = lane + 256; i < ne; i += 64) {
-        const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i) * 4u);
-        if (c != kNullCode) pn_add<T, PRIV>(yl, R, c);
-    }
+    for (int i = 0; i < kPnRounds; ++i)
+        if (64 * i < ne) pn_add<T, PRIV>(yl, R, b.cr[i], null_code);
+    for (int i = 64 * kPnRounds; i < ne; i += 64)
+        pn_add<T, PRIV>(yl, R, buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u), null_code);
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -344,44 +335,71 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
 // no runtime guards around the matrix-core instructions. Two register sets
 // alternate: the loads of the wave's next tile are issued before the current
 // tile's contraction and gather.
+// The class's operands are read by each lane from the (cache-resident)
+// tables: lane (col_l, kq) holds C[B = 16 bt + col_l][k = 4 ks + kq] =
+// phase_k V^q[A_k, B] for the matrix cores and the byte offset of its x
+// element in source row k; no workgroup barrier separates the classes.
+struct PnClass {
+    const int32_t *ob_code;   // proton one-body jumps into the row for this class: (local op << 1) | sign
+    const int64_t *ob_base;   // their source rows' offsets in x
+    int a0, kp, nB;
+    uint32_t null_code;       // padding entry of the gather lists
+};
+
 template <typename T, bool PRIV, int NBT, int KST>
-__device__ __forceinline__ void pn_tiles(const T *__restrict__ Cl, const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+__device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict__ V, __amdgpu_buffer_rsrc_t xr,
                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
                                          int wid, int lane, T *__restrict__ R, T *__restrict__ yl) {
-    constexpr int CS = Lds<T>::c_stride;
     if (wid >= ntiles) return;
+    const int col_l = lane & 15, kq = lane >> 4;
+    unsigned voff[KST];
     T cv[NBT][KST];   // the class's C operand stays in registers for all tiles
 #pragma unroll
-    for (int bt = 0; bt < NBT; ++bt)
+    for (int ks = 0; ks < KST; ++ks) {
+        const int k = 4 * ks + kq;
+        const bool ok = k < pc.kp;
+        const int code = ok ? pc.ob_code[pc.a0 + k] : 0;
+        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)sizeof(T) : kOutOfRange;
 #pragma unroll
-        for (int ks = 0; ks < KST; ++ks) cv[bt][ks] = Cl[bt * 16 * CS + 4 * ks];
+        for (int bt = 0; bt < NBT; ++bt) {
+            const int B = 16 * bt + col_l;
+            const T v = ok && B < pc.nB ? V[(code >> 1) * pc.nB + B] : (T)0;
+            cv[bt][ks] = (code & 1) ? -v : v;
+        }
+    }
     PnBounds pb;
     pn_bounds(pb, 0, wid, ntiles, pnp, lane);
-    PnTile<T, KST> A, B;
+    // three register sets in rotation: tiles j+1 and j+2 are in flight while tile j is worked on
+    constexpr int W = kT / 64;
+    PnTile<T, KST> A, B, C;
     pn_fetch<T, KST>(A, 0, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-    for (int j = 0;; j += 2) {
-        pn_fetch<T, KST>(B, j + 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-        pn_work<T, PRIV, NBT, KST>(A, cv, cres, lane, R, yl);
-        if (wid + (kT / 64) * (j + 1) >= ntiles) break;
-        pn_fetch<T, KST>(A, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-        pn_work<T, PRIV, NBT, KST>(B, cv, cres, lane, R, yl);
-        if (wid + (kT / 64) * (j + 2) >= ntiles) break;
+    pn_fetch<T, KST>(B, 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+    for (int j = 0;; j += 3) {
+        pn_fetch<T, KST>(C, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
+        if (wid + W * (j + 1) >= ntiles) break;
+        pn_fetch<T, KST>(A, j + 3, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
+        if (wid + W * (j + 2) >= ntiles) break;
+        pn_fetch<T, KST>(B, j + 4, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_work<T, PRIV, NBT, KST>(C, cv, cres, pc.null_code, lane, R, yl);
+        if (wid + W * (j + 3) >= ntiles) break;
     }
 }
 
 template <typename T, bool PRIV, int NBT>
-__device__ __forceinline__ void pn_tiles_k(int ksteps, const T *Cl, const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+__device__ __forceinline__ void pn_tiles_k(int ksteps, const PnClass &pc, const T *V, __amdgpu_buffer_rsrc_t xr,
                                            const int32_t *pnp, __amdgpu_buffer_rsrc_t pnc, int ntiles, int wid,
                                            int lane, T *R, T *yl) {
     switch (ksteps) {
-        case 1: pn_tiles<T, PRIV, NBT, 1>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 2: pn_tiles<T, PRIV, NBT, 2>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 3: pn_tiles<T, PRIV, NBT, 3>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 4: pn_tiles<T, PRIV, NBT, 4>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 5: pn_tiles<T, PRIV, NBT, 5>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 6: pn_tiles<T, PRIV, NBT, 6>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 7: pn_tiles<T, PRIV, NBT, 7>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        default: pn_tiles<T, PRIV, NBT, 8>(Cl, voff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 1: pn_tiles<T, PRIV, NBT, 1>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 2: pn_tiles<T, PRIV, NBT, 2>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 3: pn_tiles<T, PRIV, NBT, 3>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 4: pn_tiles<T, PRIV, NBT, 4>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 5: pn_tiles<T, PRIV, NBT, 5>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 6: pn_tiles<T, PRIV, NBT, 6>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 7: pn_tiles<T, PRIV, NBT, 7>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        default: pn_tiles<T, PRIV, NBT, 8>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
     }
 }
 
@@ -389,10 +407,7 @@ __device__ __forceinline__ void pn_tiles_k(int ksteps, const T *Cl, const unsign
 // in dynamic LDS, summed at the end); otherwise one shared row with atomics.
 template <typename T, bool PRIV>
 __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
-    constexpr int CS = Lds<T>::c_stride;
-    __shared__ __align__(16) T Rw[kT / 64][Lds<T>::r_words];
-    __shared__ T C[kNB * CS];
-    __shared__ int32_t srcb[kKP];
+    __shared__ __align__(16) T Rw[kT / 64][kPnTile * kPnRStride];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *yall = reinterpret_cast<T *>(smem_raw);   // output row(s) [nn]
 
@@ -400,7 +415,6 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
     const int tid = threadIdx.x;
     // the wave index is uniform across the wave: keep it (and the tile loop) scalar
     const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int col_l = lane & 15, kq = lane >> 4;
     const int s = P.p_sector[ip];
     const int nn = P.sec_nn[s];
     const int64_t base = P.p_pstart[ip];
@@ -412,11 +426,16 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
     const __amdgpu_buffer_rsrc_t cres =
         __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn_code, (short)0, (int)(TT.n_pn_code * 4), kBufFlags);
     T *R = Rw[wid];
-    const int ystride = TT.max_nn;
+    const int ystride = TT.max_nn + 1;   // one padding column per row
     T *yl = PRIV ? yall + wid * ystride : yall;
     for (int w = 0; w < (PRIV ? kT / 64 : 1); ++w)
         for (int c = tid; c < nn; c += kT) yall[w * ystride + c] = 0;
+    __syncthreads();
     bool any = false;
+    PnClass pc;
+    pc.ob_code = P.p.ob_code;
+    pc.ob_base = TT.p_ob_base;
+    pc.null_code = TT.pn_null;
     for (int q = 0; q < nq; ++q) {
         const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q], a1 = P.p.ob_ptr[(int64_t)ip * nq + q + 1];
         if (a0 == a1) continue;   // uniform across the workgroup
@@ -427,36 +446,17 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
         const T *V = vq + P.vq_off[q];
         const int nns = P.sec_nn[P.p_sector[P.p.ob_src[a0]]];
         const int64_t pslot = ((int64_t)s * nq + qn) * ntl;
-        const int kp = a1 - a0;
-        // C[B][k] = phase_k V^q[A_k, B] and the source row offsets
-        __syncthreads();
-        for (int t = tid; t < kKP; t += kT) srcb[t] = t < kp ? (int32_t)TT.p_ob_base[a0 + t] : -1;
-        for (int idx = tid; idx < kNB * CS; idx += kT) {
-            const int B = idx / CS, k = idx - B * CS;
-            T v = 0;
-            if (B < nB && k < kp) {
-                const int code = P.p.ob_code[a0 + k];
-                v = V[(code >> 1) * nB + B];
-                if (code & 1) v = -v;
-            }
-            C[idx] = v;
-        }
-        __syncthreads();
-        const int ksteps = (kp + 3) >> 2;
+        pc.a0 = a0;
+        pc.kp = a1 - a0;
+        pc.nB = nB;
+        const int ksteps = (pc.kp + 3) >> 2;
         const int ntiles = (nns + 15) >> 4;
-        unsigned voff[8];
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int sb = srcb[4 * ks + kq];
-            voff[ks] = sb >= 0 ? (unsigned)(sb + col_l) * (unsigned)sizeof(T) : kOutOfRange;
-        }
-        const T *Cl = C + col_l * CS + kq;
         const int32_t *pnp = TT.pn_ptr + pslot;
         switch (nbt) {
-            case 1: pn_tiles_k<T, PRIV, 1>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            case 2: pn_tiles_k<T, PRIV, 2>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            case 3: pn_tiles_k<T, PRIV, 3>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            default: pn_tiles_k<T, PRIV, 4>(ksteps, Cl, voff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 1: pn_tiles_k<T, PRIV, 1>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 2: pn_tiles_k<T, PRIV, 2>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 3: pn_tiles_k<T, PRIV, 3>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            default: pn_tiles_k<T, PRIV, 4>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
         }
     }
     if (!any) return;
@@ -499,14 +499,15 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[2], st), "event");
     // float: wave-private output rows (plain LDS adds) when they fit; LDS
     // float atomics are far slower than a read and a write
-    const size_t lds_priv = (size_t)(kT / 64) * t.max_nn * sizeof(T);
+    const size_t lds_priv = (size_t)(kT / 64) * (t.max_nn + 1) * sizeof(T);
     bool priv = false;
     if constexpr (sizeof(T) == 4) {
         priv = lds_priv <= 32768;
         if (priv) hipLaunchKernelGGL((k_pn<T, true>), dim3(d.p.n_sd), dim3(kT), lds_priv, st, d, t, x, y);
     }
     if (!priv)
-        hipLaunchKernelGGL((k_pn<T, false>), dim3(d.p.n_sd), dim3(kT), (size_t)t.max_nn * sizeof(T), st, d, t, x, y);
+        hipLaunchKernelGGL((k_pn<T, false>), dim3(d.p.n_sd), dim3(kT), (size_t)(t.max_nn + 1) * sizeof(T), st, d, t,
+                           x, y);
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[3], st), "event");
 }
 
