@@ -161,21 +161,26 @@ struct DevTiled {
     int32_t n_rtiles, n_ctiles, rt_rows, ct_cols;
     // pn neutron gather lists grouped by (destination sector, neutron class, 16-column source tile)
     const int32_t *pn_ptr;       // [(n_sectors*nq)*n_t16 + 1]
-    const uint32_t *pn_code;     // (phase < 0) << 31 | dst col << 11 | R element; rounds of 64 entries with
-                                 // distinct destinations, padded with pn_null (R element 0, dst col max_nn)
+    const uint32_t *pn_code;     // (phase < 0) << 31 | dst col << kPnRBits | R element; rounds of 64 entries
+                                 // with distinct destinations, padded with pn_null (R element 0, dst col max_nn)
     int64_t n_pn_code;           // entries of pn_code (a multiple of 64)
     uint32_t pn_null;            // padding code
-    int32_t n_t16;               // tiles per sector slot (ceil(max nn / 16))
+    int32_t n_t16;               // tiles per sector slot (ceil(max nn / kPnTile))
     int32_t kp_pad;              // max proton one-body jumps into a row per class, rounded up to 4
     int32_t max_nn, max_np;
     int32_t ok;
 };
 
-// The pn kernel's per-wave tile R holds, for 16 source columns of a tile and
-// up to 64 neutron labels B, the partial sums R[B][col] column-major with
-// column stride kPnRStride; a gather code names its R element col * kPnRStride + B.
-constexpr int kPnTile = 16;
+// The pn kernel's per-wave tile R holds, for the kPnTile source columns of a
+// tile and up to 64 neutron labels B, the partial sums R[B][col] column-major
+// with column stride kPnRStride; a gather code names its R element
+// col * kPnRStride + B in its low kPnRBits bits, the destination column in
+// the bits above, and the phase in bit 31.
+constexpr int kPnTile = 32;                 // source columns per tile (a multiple of 16)
 constexpr int kPnRStride = 68;
+constexpr int kPnRBits = 12;                // kPnTile * kPnRStride <= 1 << kPnRBits
+constexpr int kPnDstBits = 31 - kPnRBits;
+constexpr int kPnWaves = 2;                 // waves per pn workgroup
 
 struct HostTiled {
     std::vector<int32_t> order, nn_ell_E, nn_ell_src, nn_ell_ent, pp_ell_E, pp_ell_src, pp_ell_ent;

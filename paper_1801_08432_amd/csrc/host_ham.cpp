@@ -143,15 +143,16 @@ void build_tiled_tables(fotci_ham *h) {
         }
     }
     // pn gather lists: neutron one-body jumps into the columns of each
-    // destination sector, grouped by (neutron class, 16-column source tile)
+    // destination sector, grouped by (neutron class, kPnTile-column source tile)
     t.n_t16 = (t.max_nn + kTL - 1) / kTL;
     const int nch = std::max(t.n_t16, 1);
     int kpmax = 1;
     for (size_t i = 0; i + 1 < h->tp.ob_ptr.size(); ++i) kpmax = std::max(kpmax, h->tp.ob_ptr[i + 1] - h->tp.ob_ptr[i]);
     t.kp_pad = (kpmax + 3) & ~3;
     // up to 32 proton jumps per class in the pn kernel; x addressed with 32-bit byte offsets
-    // destination columns (and one padding column) in 20 bits of a gather code
-    if (kpmax > 32 || b->dim * 8 >= ((int64_t)1 << 31) || t.max_nn >= (1 << 20) - 1) ok = false;
+    // destination columns (and one padding column) in kPnDstBits bits of a gather code
+    static_assert(kPnTile * kPnRStride <= (1 << kPnRBits), "R element must fit its code field");
+    if (kpmax > 32 || b->dim * 8 >= ((int64_t)1 << 31) || t.max_nn >= (1 << kPnDstBits) - 1) ok = false;
     std::vector<int32_t> nsec_to_bsec(b->n.sectors.size(), -1);
     for (int s = 0; s < S; ++s) nsec_to_bsec[b->sectors[s].n_sector] = s;
     const auto &rec = h->j->rec[FOTCI_JUMP_N1];
@@ -180,7 +181,7 @@ void build_tiled_tables(fotci_ham *h) {
     // columns (one round = one LDS instruction of a wave, so no two lanes add
     // to the same address); every round is padded to 64 entries with the
     // null code, which adds R element 0 to the padding column max_nn.
-    const uint32_t null_code = (uint32_t)t.max_nn << 11;
+    const uint32_t null_code = (uint32_t)t.max_nn << kPnRBits;
     t.pn_ptr.assign(cnt.size(), 0);
     t.pn_code.clear();
     std::vector<std::vector<uint32_t>> rounds;
@@ -195,7 +196,8 @@ void build_tiled_tables(fotci_ham *h) {
             const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kTL);
             const uint32_t B = (uint32_t)cl.local_of[r.label];
             // sign << 31 | destination column << 11 | R element (source offset in the tile, label B)
-            const uint32_t code = (r.phase < 0 ? 0x80000000u : 0u) | (dcol << 11) | (so * (uint32_t)kPnRStride + B);
+            const uint32_t code =
+                (r.phase < 0 ? 0x80000000u : 0u) | (dcol << kPnRBits) | (so * (uint32_t)kPnRStride + B);
             size_t g = 0;
             for (; g < rounds.size(); ++g) {
                 if (rounds[g].size() >= 64) continue;
@@ -382,7 +384,7 @@ std::vector<Item> items(fotci_ham *h) {
     dt.ct_cols = 8;
     dt.n_t16 = std::max(tt.n_t16, 1);
     dt.n_pn_code = (int64_t)tt.pn_code.size();
-    dt.pn_null = (uint32_t)tt.max_nn << 11;
+    dt.pn_null = (uint32_t)tt.max_nn << kPnRBits;
     dt.kp_pad = tt.kp_pad;
     dt.max_nn = tt.max_nn;
     dt.max_np = tt.max_np;

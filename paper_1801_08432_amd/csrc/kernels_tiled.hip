@@ -185,12 +185,14 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
 }
 
 // ---------------------------------------------------------------------- pn
-// Waves work independently on 16-column source tiles: each contracts its tile
-// on the matrix cores into a wave-private slice of R in LDS and gathers the
-// neutron jumps whose source lies in the tile into the shared output row.
-// Only the per-class staging of C needs a workgroup barrier. x is read with
-// buffer loads: each lane's offset is fixed for the whole class and the tile
-// offset is scalar; padding lanes point past the end of x and read zero.
+// Waves work independently on kPnTile-column source tiles: each contracts its
+// tile on the matrix cores (16 columns per instruction) into a wave-private
+// R in LDS and gathers the neutron jumps whose source lies in the tile into
+// its output row. x is read with buffer loads: each lane's offset is fixed
+// for the whole class and the tile offset is scalar; padding lanes point past
+// the end of x and read zero.
+constexpr int kPnThreads = 64 * kPnWaves;
+constexpr int kPnHalves = kPnTile / 16;   // 16-column matrix-core blocks per tile
 constexpr unsigned kBufFlags = 0x00020000u;   // raw buffer, 32-bit data format
 constexpr unsigned kOutOfRange = 0x7ff00000u;  // byte offset beyond any x
 
@@ -213,24 +215,26 @@ __device__ __forceinline__ double signed_by(double v, uint32_t code) {
 }
 
 
-// LDS layout of the per-wave tile R[B][col] (B < 64 neutron labels, col < 16
-// source columns): column-major with column stride kPnRStride = 68 elements.
-// float: a lane's four accumulator rows (4 consecutive B) leave in one
-// 16-byte store, and 8 lanes of a store cover all 32 banks. double: the
-// accumulator rows of a lane are 4 apart and leave in four stores.
+// LDS layout of the per-wave tile R[B][col] (B < 64 neutron labels, col <
+// kPnTile source columns): column-major with column stride kPnRStride = 68
+// elements. float: a lane's four accumulator rows (4 consecutive B) leave in
+// one 16-byte store, and 8 lanes of a store cover all 32 banks. double: the
+// accumulator rows of a lane are 4 apart and leave in four stores. h selects
+// the 16-column block of the tile.
 template <typename T>
 struct Lds;
 template <>
 struct Lds<float> {
-    static __device__ __forceinline__ void store(float *R, int lane, int bt, const floatx4 &acc) {
-        *(floatx4 *)(R + (lane & 15) * kPnRStride + 16 * bt + 4 * (lane >> 4)) = acc;
+    static __device__ __forceinline__ void store(float *R, int lane, int h, int bt, const floatx4 &acc) {
+        *(floatx4 *)(R + ((lane & 15) + 16 * h) * kPnRStride + 16 * bt + 4 * (lane >> 4)) = acc;
     }
 };
 template <>
 struct Lds<double> {
-    static __device__ __forceinline__ void store(double *R, int lane, int bt, const doublex4 &acc) {
+    static __device__ __forceinline__ void store(double *R, int lane, int h, int bt, const doublex4 &acc) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) R[(lane & 15) * kPnRStride + 16 * bt + Mma<double>::row(lane, r)] = acc[r];
+        for (int r = 0; r < 4; ++r)
+            R[((lane & 15) + 16 * h) * kPnRStride + 16 * bt + Mma<double>::row(lane, r)] = acc[r];
     }
 };
 
@@ -238,15 +242,15 @@ __device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, un
     return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0);
 }
 
-// The loads of one 16-column source tile: KST x values per lane and the first
-// 256 gather codes. Their number is fixed and no lane skips them (buffer
+// The loads of one source tile: KST x values per lane for each 16-column
+// block and the first kPnRounds rounds of gather codes. Their number is fixed and no lane skips them (buffer
 // loads past a range return 0), so the compiler can count them and let the
 // next tile's loads stay in flight while the current tile is worked on.
 constexpr int kPnRounds = 8;   // gather rounds of a tile loaded with its x values
 
 template <typename T, int KST>
 struct PnTile {
-    T xv[KST];
+    T xv[kPnHalves][KST];
     uint32_t cr[kPnRounds];
     int e0, e1;
 };
@@ -260,7 +264,7 @@ struct PnBounds {
 
 __device__ __forceinline__ void pn_bounds(PnBounds &pb, int j0, int wid, int ntiles, const int32_t *__restrict__ pnp,
                                           int lane) {
-    const int tt = wid + (kT / 64) * (j0 + lane);
+    const int tt = wid + kPnWaves * (j0 + lane);
     pb.b0 = pnp[min(tt, ntiles)];
     pb.b1 = pnp[min(tt + 1, ntiles)];
 }
@@ -272,13 +276,16 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
                                          const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int lane) {
     if (j > 0 && (j & 63) == 0) pn_bounds(pb, j, wid, ntiles, pnp, lane);   // uniform, every 64 tiles
-    const int tt = wid + (kT / 64) * j;
+    const int tt = wid + kPnWaves * j;
     const int tc = min(tt, ntiles - 1);
     b.e0 = __builtin_amdgcn_readlane(pb.b0, j & 63);
     b.e1 = tt < ntiles ? __builtin_amdgcn_readlane(pb.b1, j & 63) : b.e0;
-    const unsigned soff = (unsigned)(16 * tc) * (unsigned)sizeof(T);
+    const unsigned soff = (unsigned)(kPnTile * tc) * (unsigned)sizeof(T);
 #pragma unroll
-    for (int ks = 0; ks < KST; ++ks) b.xv[ks] = buffer_load<T>(xr, voff[ks], soff);
+    for (int h = 0; h < kPnHalves; ++h)
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks)
+            b.xv[h][ks] = buffer_load<T>(xr, voff[ks], soff + (unsigned)(16 * h * sizeof(T)));
 #pragma unroll
     for (int i = 0; i < kPnRounds; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
 }
@@ -288,11 +295,12 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
 // the padding column); with the shared row it is skipped.
 template <typename T, bool PRIV>
 __device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__ R, uint32_t c, uint32_t null_code) {
-    const T v = signed_by(R[c & 0x7ffu], c);
+    const T v = signed_by(R[c & ((1u << kPnRBits) - 1u)], c);
+    const uint32_t d = (c >> kPnRBits) & ((1u << kPnDstBits) - 1u);
     if (PRIV)
-        yl[(c >> 11) & 0xfffffu] += v;
+        yl[d] += v;
     else if (c != null_code)
-        atomicAdd(&yl[(c >> 11) & 0xfffffu], v);
+        atomicAdd(&yl[d], v);
 }
 
 // Contraction and gather of one fetched tile; cv holds the class's C operand.
@@ -306,15 +314,21 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
                                         T *__restrict__ R, T *__restrict__ yl) {
     typedef typename Mma<T>::acc_t acc_t;
     if (b.e0 == b.e1) return;   // uniform: no neutron jump leaves this tile
-    acc_t acc[NBT];
+    acc_t acc[kPnHalves][NBT];
 #pragma unroll
-    for (int bt = 0; bt < NBT; ++bt) acc[bt] = Mma<T>::zero();
+    for (int h = 0; h < kPnHalves; ++h)
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) acc[h][bt] = Mma<T>::zero();
 #pragma unroll
     for (int ks = 0; ks < KST; ++ks)
 #pragma unroll
-        for (int bt = 0; bt < NBT; ++bt) acc[bt] = Mma<T>::mma(cv[bt][ks], b.xv[ks], acc[bt]);
+        for (int h = 0; h < kPnHalves; ++h)
 #pragma unroll
-    for (int bt = 0; bt < NBT; ++bt) Lds<T>::store(R, lane, bt, acc[bt]);
+            for (int bt = 0; bt < NBT; ++bt) acc[h][bt] = Mma<T>::mma(cv[bt][ks], b.xv[h][ks], acc[h][bt]);
+#pragma unroll
+    for (int h = 0; h < kPnHalves; ++h)
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) Lds<T>::store(R, lane, h, bt, acc[h][bt]);
     // a wave's LDS operations complete in issue order: the gather below
     // sees the stores above without a workgroup barrier
     __builtin_amdgcn_wave_barrier();
@@ -369,21 +383,35 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
     }
     PnBounds pb;
     pn_bounds(pb, 0, wid, ntiles, pnp, lane);
-    // three register sets in rotation: tiles j+1 and j+2 are in flight while tile j is worked on
-    constexpr int W = kT / 64;
-    PnTile<T, KST> A, B, C;
-    pn_fetch<T, KST>(A, 0, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-    pn_fetch<T, KST>(B, 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-    for (int j = 0;; j += 3) {
-        pn_fetch<T, KST>(C, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-        pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
-        if (wid + W * (j + 1) >= ntiles) break;
-        pn_fetch<T, KST>(A, j + 3, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-        pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
-        if (wid + W * (j + 2) >= ntiles) break;
-        pn_fetch<T, KST>(B, j + 4, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-        pn_work<T, PRIV, NBT, KST>(C, cv, cres, pc.null_code, lane, R, yl);
-        if (wid + W * (j + 3) >= ntiles) break;
+    constexpr int W = kPnWaves;
+    if constexpr (sizeof(T) == 4) {
+        // three register sets in rotation: tiles j+1 and j+2 are in flight while tile j is worked on
+        PnTile<T, KST> A, B, C;
+        pn_fetch<T, KST>(A, 0, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_fetch<T, KST>(B, 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        for (int j = 0;; j += 3) {
+            pn_fetch<T, KST>(C, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
+            if (wid + W * (j + 1) >= ntiles) break;
+            pn_fetch<T, KST>(A, j + 3, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
+            if (wid + W * (j + 2) >= ntiles) break;
+            pn_fetch<T, KST>(B, j + 4, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_work<T, PRIV, NBT, KST>(C, cv, cres, pc.null_code, lane, R, yl);
+            if (wid + W * (j + 3) >= ntiles) break;
+        }
+    } else {
+        // double: two register sets (the operands are twice as wide)
+        PnTile<T, KST> A, B;
+        pn_fetch<T, KST>(A, 0, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        for (int j = 0;; j += 2) {
+            pn_fetch<T, KST>(B, j + 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
+            if (wid + W * (j + 1) >= ntiles) break;
+            pn_fetch<T, KST>(A, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
+            if (wid + W * (j + 2) >= ntiles) break;
+        }
     }
 }
 
@@ -403,11 +431,13 @@ __device__ __forceinline__ void pn_tiles_k(int ksteps, const PnClass &pc, const 
     }
 }
 
-// PRIV: each wave accumulates into its own output row (kT/64 rows of max_nn
-// in dynamic LDS, summed at the end); otherwise one shared row with atomics.
+// PRIV: each wave accumulates into its own output row (kPnWaves rows of
+// max_nn + 1 in dynamic LDS, summed at the end); otherwise one shared row
+// with atomics.
 template <typename T, bool PRIV>
-__global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
-    __shared__ __align__(16) T Rw[kT / 64][kPnTile * kPnRStride];
+__global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const T *__restrict__ x,
+                                                   T *__restrict__ y) {
+    __shared__ __align__(16) T Rw[kPnWaves][kPnTile * kPnRStride];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *yall = reinterpret_cast<T *>(smem_raw);   // output row(s) [nn]
 
@@ -428,8 +458,8 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
     T *R = Rw[wid];
     const int ystride = TT.max_nn + 1;   // one padding column per row
     T *yl = PRIV ? yall + wid * ystride : yall;
-    for (int w = 0; w < (PRIV ? kT / 64 : 1); ++w)
-        for (int c = tid; c < nn; c += kT) yall[w * ystride + c] = 0;
+    for (int w = 0; w < (PRIV ? kPnWaves : 1); ++w)
+        for (int c = tid; c < nn; c += kPnThreads) yall[w * ystride + c] = 0;
     __syncthreads();
     bool any = false;
     PnClass pc;
@@ -450,7 +480,7 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
         pc.kp = a1 - a0;
         pc.nB = nB;
         const int ksteps = (pc.kp + 3) >> 2;
-        const int ntiles = (nns + 15) >> 4;
+        const int ntiles = (nns + kPnTile - 1) / kPnTile;
         const int32_t *pnp = TT.pn_ptr + pslot;
         switch (nbt) {
             case 1: pn_tiles_k<T, PRIV, 1>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
@@ -461,11 +491,11 @@ __global__ __launch_bounds__(kT) void k_pn(DevHam P, DevTiled TT, const T *__res
     }
     if (!any) return;
     __syncthreads();
-    for (int c = tid; c < nn; c += kT) {
+    for (int c = tid; c < nn; c += kPnThreads) {
         T v = yall[c];
         if (PRIV)
 #pragma unroll
-            for (int w = 1; w < kT / 64; ++w) v += yall[w * ystride + c];
+            for (int w = 1; w < kPnWaves; ++w) v += yall[w * ystride + c];
         y[base + c] += v;
     }
 }
@@ -499,15 +529,15 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[2], st), "event");
     // float: wave-private output rows (plain LDS adds) when they fit; LDS
     // float atomics are far slower than a read and a write
-    const size_t lds_priv = (size_t)(kT / 64) * (t.max_nn + 1) * sizeof(T);
+    const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1) * sizeof(T);
     bool priv = false;
     if constexpr (sizeof(T) == 4) {
         priv = lds_priv <= 32768;
-        if (priv) hipLaunchKernelGGL((k_pn<T, true>), dim3(d.p.n_sd), dim3(kT), lds_priv, st, d, t, x, y);
+        if (priv) hipLaunchKernelGGL((k_pn<T, true>), dim3(d.p.n_sd), dim3(kPnThreads), lds_priv, st, d, t, x, y);
     }
     if (!priv)
-        hipLaunchKernelGGL((k_pn<T, false>), dim3(d.p.n_sd), dim3(kT), (size_t)(t.max_nn + 1) * sizeof(T), st, d, t,
-                           x, y);
+        hipLaunchKernelGGL((k_pn<T, false>), dim3(d.p.n_sd), dim3(kPnThreads), (size_t)(t.max_nn + 1) * sizeof(T), st,
+                           d, t, x, y);
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[3], st), "event");
 }
 
