@@ -210,9 +210,24 @@ int fotci_lanczos_lowest(const fotci_ham *h, const fotci_lanczos_opts *o, const 
 int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn,
                         int64_t *ops_diag);
 
+/* Work of the pn kernel of the tiled modes in one apply_H (host; no device
+ * needed), counted from the tables the kernel walks: visited (destination
+ * row, operator class, 32-column source tile) triples, 16x16x4 matrix-core
+ * instructions, and gather slots including the padding of the 64-entry
+ * rounds. Each output may be NULL. FOTCI_ESTATE when the tiled kernels are
+ * not available for this basis. */
+int fotci_ham_pn_work(const fotci_ham *h, int64_t *tile_visits, int64_t *mfma_instr, int64_t *gather_slots);
+
+/* Output-row policy of the float32 pn kernel (FOTCI_MODE_F32): 1 (default)
+ * gives each wave a private LDS output row when they fit and adds with plain
+ * LDS read-modify-write; 0 uses one shared row with LDS atomics. Both give
+ * the same sums up to rounding order; the choice changes speed only.
+ * FOTCI_EINVAL unless enable is 0 or 1. */
+int fotci_ham_set_pn_private_rows(fotci_ham *h, int32_t enable);
+
 /*
  * fotci_profile_start / fotci_profile_stop -- per-kernel timing of apply_H
- * (the paper's "mode times", Ch. 8, done with HIP events). Between start and
+ * (the per-part timings of Ch. 8, taken with HIP events). Between start and
  * stop, every fotci_apply_H call on this Hamiltonian records a HIP event on
  * its stream before its first kernel and after each kernel (max_calls calls at
  * most; later calls are not recorded). stop synchronises on the events and

@@ -55,6 +55,8 @@ extern "C" int fotci_ham_upload_impl(fotci_ham *, void *, int64_t, void *);
 extern "C" int fotci_ham_set_values_impl(fotci_ham *, const double *, const double *, const double *, const double *,
                                          const double *, void *);
 extern "C" int fotci_ham_op_counts_impl(const fotci_ham *, int64_t *, int64_t *, int64_t *, int64_t *);
+extern "C" int fotci_ham_pn_work_impl(const fotci_ham *, int64_t *, int64_t *, int64_t *);
+extern "C" int fotci_ham_set_pn_private_rows_impl(fotci_ham *, int32_t);
 
 extern "C" {
 
@@ -205,6 +207,14 @@ int fotci_lanczos_lowest(const fotci_ham *h, const fotci_lanczos_opts *o, const 
 
 int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn, int64_t *ops_diag) {
     return guard([&] { return fotci_ham_op_counts_impl(h, ops_pp, ops_nn, ops_pn, ops_diag); });
+}
+
+int fotci_ham_pn_work(const fotci_ham *h, int64_t *tile_visits, int64_t *mfma_instr, int64_t *gather_slots) {
+    return guard([&] { return fotci_ham_pn_work_impl(h, tile_visits, mfma_instr, gather_slots); });
+}
+
+int fotci_ham_set_pn_private_rows(fotci_ham *h, int32_t enable) {
+    return guard([&] { return fotci_ham_set_pn_private_rows_impl(h, enable); });
 }
 
 int fotci_profile_start(fotci_ham *h, int32_t max_calls) {

@@ -169,6 +169,7 @@ struct DevTiled {
     int32_t kp_pad;              // max proton one-body jumps into a row per class, rounded up to 4
     int32_t max_nn, max_np;
     int32_t ok;
+    int32_t pn_priv;             // float pn kernel: 1 = a private output row per wave when it fits, 0 = shared row
 };
 
 // The pn kernel's per-wave tile R holds, for the kPnTile source columns of a
@@ -216,6 +217,7 @@ struct fotci_ham {
     fotci::HostCommonTables tc;
     fotci::HostTiled tt;
     fotci::DevTiled dev_tiled{};
+    int32_t pn_priv = 1;                  // see fotci_ham_set_pn_private_rows
     // device
     bool uploaded = false;
     void *ws = nullptr;

@@ -376,6 +376,7 @@ std::vector<Item> items(fotci_ham *h) {
     HostTiled &tt = h->tt;
     DevTiled &dt = h->dev_tiled;
     dt.ok = tt.ok ? 1 : 0;
+    dt.pn_priv = h->pn_priv;
     dt.nn_ell_len = (int64_t)tt.nn_ell_src.size();
     dt.pp_ell_len = (int64_t)tt.pp_ell_src.size();
     dt.n_rtiles = (int32_t)tt.rt_sec.size();
@@ -552,5 +553,51 @@ extern "C" int fotci_ham_op_counts_impl(const fotci_ham *h, int64_t *ops_pp, int
     if (ops_nn) *ops_nn = nn;
     if (ops_pn) *ops_pn = pn;
     if (ops_diag) *ops_diag = b->dim;
+    return FOTCI_OK;
+}
+
+// Work of the pn kernel in one apply_H, from the same tables and in the same
+// order the kernel visits them: per destination row and operator class with
+// proton jumps, every source tile whose gather list is not empty.
+extern "C" int fotci_ham_pn_work_impl(const fotci_ham *h, int64_t *tile_visits, int64_t *mfma_instr,
+                                      int64_t *gather_slots) {
+    if (!h) fail(FOTCI_EINVAL, "NULL handle");
+    const HostTiled &t = h->tt;
+    if (!t.ok) fail(FOTCI_ESTATE, "the tiled kernels are not available for this basis");
+    const fotci_basis *b = h->j->b;
+    const int nq = h->j->cls.nq;
+    const int ntl = std::max(t.n_t16, 1);
+    const auto &tc = h->tc;
+    int64_t visits = 0, mfma = 0, slots = 0;
+    for (int ip = 0; ip < (int)b->p.sd.size(); ++ip) {
+        const int s = tc.p_sector[ip];
+        for (int q = 0; q < nq; ++q) {
+            const int a0 = h->tp.ob_ptr[(size_t)ip * nq + q], a1 = h->tp.ob_ptr[(size_t)ip * nq + q + 1];
+            if (a0 == a1) continue;
+            const int qn = h->j->cls.conj[q];
+            const int nbt = (h->vq_nb[q] + 15) / 16;
+            const int kst = (a1 - a0 + 3) / 4;
+            const int nns = tc.sec_nn[tc.p_sector[h->tp.ob_src[a0]]];
+            const int ntiles = (nns + kPnTile - 1) / kPnTile;
+            const int64_t base = ((int64_t)s * nq + qn) * ntl;
+            for (int tt = 0; tt < ntiles; ++tt) {
+                const int64_t ne = t.pn_ptr[base + tt + 1] - t.pn_ptr[base + tt];
+                if (ne == 0) continue;
+                visits += 1;
+                mfma += (int64_t)(kPnTile / 16) * nbt * kst;
+                slots += ne;
+            }
+        }
+    }
+    if (tile_visits) *tile_visits = visits;
+    if (mfma_instr) *mfma_instr = mfma;
+    if (gather_slots) *gather_slots = slots;
+    return FOTCI_OK;
+}
+
+extern "C" int fotci_ham_set_pn_private_rows_impl(fotci_ham *h, int32_t enable) {
+    if (!h || (enable != 0 && enable != 1)) fail(FOTCI_EINVAL, "bad argument");
+    h->pn_priv = enable;
+    h->dev_tiled.pn_priv = enable;
     return FOTCI_OK;
 }

@@ -532,7 +532,7 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
     const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1) * sizeof(T);
     bool priv = false;
     if constexpr (sizeof(T) == 4) {
-        priv = lds_priv <= 32768;
+        priv = t.pn_priv && lds_priv <= 32768;
         if (priv) hipLaunchKernelGGL((k_pn<T, true>), dim3(d.p.n_sd), dim3(kPnThreads), lds_priv, st, d, t, x, y);
     }
     if (!priv)

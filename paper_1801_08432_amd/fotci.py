@@ -27,7 +27,8 @@ EXPORTED = [
     "fotci_basis_export", "fotci_build_jumps", "fotci_free_jumps", "fotci_jumps_count", "fotci_jumps_export",
     "fotci_set_interaction", "fotci_free_ham", "fotci_ham_set_values", "fotci_ham_workspace_bytes",
     "fotci_ham_upload", "fotci_apply_H", "fotci_apply_H_vjp", "fotci_lanczos_workspace_bytes",
-    "fotci_lanczos_lowest", "fotci_ham_op_counts", "fotci_tridiag_eigh", "fotci_profile_start",
+    "fotci_lanczos_lowest", "fotci_ham_op_counts", "fotci_ham_pn_work", "fotci_ham_set_pn_private_rows",
+    "fotci_tridiag_eigh", "fotci_profile_start",
     "fotci_profile_stop",
 ]
 
@@ -76,6 +77,8 @@ def lib():
         "fotci_lanczos_workspace_bytes": (I64, [P, P]),
         "fotci_lanczos_lowest": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P, P]),
         "fotci_ham_op_counts": (ctypes.c_int, [P, P, P, P, P]),
+        "fotci_ham_pn_work": (ctypes.c_int, [P, P, P, P]),
+        "fotci_ham_set_pn_private_rows": (ctypes.c_int, [P, ctypes.c_int32]),
         "fotci_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
         "fotci_profile_start": (ctypes.c_int, [P, I32]),
         "fotci_profile_stop": (ctypes.c_int, [P, P, P, P, P]),
@@ -222,6 +225,15 @@ class Hamiltonian:
         v = [ctypes.c_int64() for _ in range(4)]
         _check(lib().fotci_ham_op_counts(self._h, *[ctypes.byref(x) for x in v]))
         return dict(pp=v[0].value, nn=v[1].value, pn=v[2].value, diag=v[3].value)
+
+    def pn_work(self):
+        """Visited tiles, matrix-core instructions and gather slots of the pn kernel per apply."""
+        v = [ctypes.c_int64() for _ in range(3)]
+        _check(lib().fotci_ham_pn_work(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(tile_visits=v[0].value, mfma_instr=v[1].value, gather_slots=v[2].value)
+
+    def set_pn_private_rows(self, enable):
+        _check(lib().fotci_ham_set_pn_private_rows(self._h, 1 if enable else 0))
 
     def apply(self, x, y=None, mode="f64", stream=None):
         """y = H x on the device (x: float64 for f64 modes, float32 otherwise)."""

@@ -63,6 +63,22 @@ def test_apply_f32_matches_oracle(name):
     assert rel_l2(y, ref) <= 1e-5
 
 
+def test_apply_f32_shared_row_policy():
+    """The float32 pn kernel with one shared LDS output row (atomics) and with
+    private rows per wave: both match the oracle to float32 rounding."""
+    w, h, o, prep = setup("sd_6p6n")
+    x = inputs.random_vector(h.dim, 13)
+    xt = torch.from_numpy(x).float().to(DEV)
+    y1 = h.apply(xt, mode="f32").double().cpu().numpy()
+    h.set_pn_private_rows(False)
+    try:
+        y0 = h.apply(xt, mode="f32").double().cpu().numpy()
+    finally:
+        h.set_pn_private_rows(True)
+    ref = of.apply_h(prep, w, x.astype(np.float32).astype(np.float64))
+    assert rel_l2(y0, ref) <= 1e-5 and rel_l2(y1, ref) <= 1e-5
+
+
 def test_apply_full_size_sampled_rows():
     """pf_5p5n (dim 18.6M): every row of three windows (first sector, the
     middle of the largest sector, the last rows) against the oracle."""

@@ -162,3 +162,63 @@ def test_op_counts_pin():
         c = h.op_counts()
         tot = c["pp"] + c["nn"] + c["pn"] + c["diag"]
         assert 0.85 * printed < tot < 1.15 * printed, (c, tot)
+
+
+@pytest.mark.parametrize("name", ["sd_2p2n", "sd_6p6n"])
+def test_pn_work_counts(name):
+    """The pn kernel's work counts, recomputed from the exported jump lists:
+    a (destination row, class, 32-column source tile) is visited when the row
+    has proton jumps of the class and some neutron jump of the conjugate
+    class leaves the tile into the row's neutron sector; it costs
+    2 * ceil(n_B / 16) * ceil(k_p / 4) matrix-core instructions; its gather
+    list is a whole number of 64-entry rounds, at least as many as its
+    largest number of entries sharing a destination column."""
+    w = inputs.WORKLOADS[name]
+    space = w["two_j"]
+    inter, _ = inputs.random_interaction(space, 3)
+    h = fotci.Hamiltonian.build(space, w["Z"], w["N"], w["two_M"], inter, upload=False)
+    got = h.pn_work()
+    b, j = h.basis, h.jumps
+    e = b.export()
+    ms = ob.m_states(space)
+    tm = np.array([m[2] for m in ms])
+    ns = len(ms)
+    p_sec = np.zeros(b.n_psd, int)
+    n_sec = np.zeros(b.n_nsd, int)
+    n_loc = np.zeros(b.n_nsd, int)
+    for si, (m2, par, pf, npp, nf, nnn, off) in enumerate(e["sectors"]):
+        p_sec[pf:pf + npp] = si
+        n_sec[nf:nf + nnn] = si
+        n_loc[nf:nf + nnn] = np.arange(nnn)
+    P1, N1 = j.export(fotci.JUMP_P1), j.export(fotci.JUMP_N1)
+    dP = tm[P1[:, 3] // ns] - tm[P1[:, 3] % ns]
+    dN = tm[N1[:, 3] // ns] - tm[N1[:, 3] % ns]
+    n_ops = {d: len(set(N1[dN == d, 3].tolist())) for d in set(dN.tolist())}
+    # neutron entries per (destination sector, delta, source tile): count and largest destination multiplicity
+    tiles = {}   # (destination sector, delta) -> source tile -> destination columns
+    for (src, dst, ph, lab), d in zip(N1.tolist(), dN.tolist()):
+        tiles.setdefault((n_sec[dst], d), {}).setdefault(n_loc[src] // 32, []).append(n_loc[dst])
+    visits = mfma = lo = hi = 0
+    kp = {}
+    for (src, dst, ph, lab), d in zip(P1.tolist(), dP.tolist()):
+        kp[(dst, d)] = kp.get((dst, d), 0) + 1
+    for (row, d), k in kp.items():
+        for ent in tiles.get((p_sec[row], -d), {}).values():
+            visits += 1
+            mfma += 2 * (-(-n_ops[-d] // 16)) * (-(-k // 4))
+            mult = max(np.unique(ent, return_counts=True)[1])
+            lo += 64 * max(-(-len(ent) // 64), mult)
+            hi += 64 * len(ent)
+    assert got["tile_visits"] == visits and got["mfma_instr"] == mfma
+    assert got["gather_slots"] % 64 == 0 and lo <= got["gather_slots"] <= hi
+
+
+def test_pn_private_rows_argument():
+    w = inputs.WORKLOADS["sd_2p2n"]
+    inter, _ = inputs.random_interaction(w["two_j"], 3)
+    h = fotci.Hamiltonian.build(w["two_j"], w["Z"], w["N"], w["two_M"], inter, upload=False)
+    h.set_pn_private_rows(False)
+    h.set_pn_private_rows(True)
+    with pytest.raises(fotci.FotciError) as ei:
+        fotci._check(fotci.lib().fotci_ham_set_pn_private_rows(h._h, 2))
+    assert ei.value.code == -1   # FOTCI_EINVAL
