@@ -315,3 +315,68 @@ int orc_densities(int ns, const int *two_m, const int *par,
     ctx_free(&c);
     return bad ? -1 : 0;
 }
+
+/* One-body transition densities rho_p[a*ns + c] = <g| p+_a p_c |x> and
+ * rho_n likewise (Ch. 5, "One-body density matrices", before J coupling):
+ * every basis state, every occupied c and every a with the same 2m and
+ * parity, by direct operator action. */
+int orc_one_body_densities(int ns, const int *two_m, const int *par,
+                           int n_sectors, const int64_t *sectab,
+                           int n_psd, const uint32_t *p_masks, int n_nsd, const uint32_t *n_masks,
+                           const double *g, const double *x, double *rho_p, double *rho_n, int nthreads)
+{
+    ctx_t c;
+    int bad = 0;
+    ctx_init(&c, ns, n_sectors, sectab, n_psd, p_masks, n_nsd, n_masks);
+    const int64_t dim = sectab[7 * (n_sectors - 1) + 6] + sectab[7 * (n_sectors - 1) + 3] * sectab[7 * (n_sectors - 1) + 5];
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    memset(rho_p, 0, sizeof(double) * ns * ns);
+    memset(rho_n, 0, sizeof(double) * ns * ns);
+
+#pragma omp parallel reduction(|:bad)
+    {
+        double *lp = (double *)calloc((size_t)2 * ns * ns, sizeof(double));
+        double *ln = lp + ns * ns;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t s = 0; s < dim; ++s) {
+            double xs = x[s];
+            if (xs == 0.0) continue;
+            int sec = find_sector(&c, s);
+            const int64_t *st = sectab + 7 * sec;
+            int64_t l = s - st[6];
+            int ip = (int)(st[2] + l / st[5]);
+            int jn = (int)(st[4] + l % st[5]);
+            uint32_t pm = p_masks[ip], nm = n_masks[jn];
+            for (int cc = 0; cc < ns; ++cc)
+                for (int a = 0; a < ns; ++a) {
+                    if (two_m[a] != two_m[cc] || par[a] != par[cc]) continue;
+                    uint32_t m2;
+                    int sg;
+                    if ((pm >> cc) & 1u) {
+                        sg = op_one_body(pm, a, cc, &m2);
+                        if (sg) {
+                            int r = c.p_rank[m2];
+                            if (r < 0) bad = 1;
+                            else lp[a * ns + cc] += sg * g[c.pstart[r] + c.nstart[jn]] * xs;
+                        }
+                    }
+                    if ((nm >> cc) & 1u) {
+                        sg = op_one_body(nm, a, cc, &m2);
+                        if (sg) {
+                            int r = c.n_rank[m2];
+                            if (r < 0) bad = 1;
+                            else ln[a * ns + cc] += sg * g[c.pstart[ip] + c.nstart[r]] * xs;
+                        }
+                    }
+                }
+        }
+#pragma omp critical
+        for (int k = 0; k < ns * ns; ++k) {
+            rho_p[k] += lp[k];
+            rho_n[k] += ln[k];
+        }
+        free(lp);
+    }
+    ctx_free(&c);
+    return bad ? -1 : 0;
+}

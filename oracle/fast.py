@@ -28,6 +28,9 @@ def lib():
         l.orc_densities.argtypes = [ctypes.c_int, p, p, ctypes.c_int, p, ctypes.c_int, p,
                                     ctypes.c_int, p, p, p, p, ctypes.c_int]
         l.orc_densities.restype = ctypes.c_int
+        l.orc_one_body_densities.argtypes = [ctypes.c_int, p, p, ctypes.c_int, p, ctypes.c_int, p,
+                                             ctypes.c_int, p, p, p, p, p, ctypes.c_int]
+        l.orc_one_body_densities.restype = ctypes.c_int
         _lib = l
     return _lib
 
@@ -104,6 +107,21 @@ def densities(prep, g, x, nthreads=0):
     np.add.at(d_eps_p, prep.orbit, ep)
     np.add.at(d_eps_n, prep.orbit, en)
     return dict(d_eps_p=d_eps_p, d_eps_n=d_eps_n, d_v_pp=vpp, d_v_nn=vnn, d_v_pn=vpn)
+
+
+def one_body_densities(prep, g, x, nthreads=0):
+    """Same (rho_p, rho_n) as hamiltonian.one_body_densities, computed in C."""
+    ns = prep.ns
+    rp = np.zeros(ns * ns)
+    rn = np.zeros(ns * ns)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    rc = lib().orc_one_body_densities(ns, _ptr(prep.two_m), _ptr(prep.par), len(prep.sectab), _ptr(prep.sectab),
+                                      len(prep.p_masks), _ptr(prep.p_masks), len(prep.n_masks),
+                                      _ptr(prep.n_masks), _ptr(g), _ptr(x), _ptr(rp), _ptr(rn), nthreads)
+    if rc != 0:
+        raise AssertionError("operator left the basis")
+    return rp.reshape(ns, ns), rn.reshape(ns, ns)
 
 
 class Operator:

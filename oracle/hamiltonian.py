@@ -178,6 +178,39 @@ def densities(b, g, x):
     return out
 
 
+def one_body_densities(b, g, x):
+    """M-scheme one-body transition densities between two vectors of basis b:
+
+      rho_p[a, c] = <g| p+_a p_c |x>,   rho_n[a, c] = <g| n+_a n_c |x>
+
+    (Ch. 5, "One-body density matrices": the proton-neutron densities from
+    which the J-reduced ones are coupled). An operator that changes Jz or
+    parity leads out of the basis, so only entries with m_a = m_c and equal
+    parities can be nonzero. For g = x = psi (unit norm) the diagonal holds
+    the occupations of the m-states (Ch. 4, "Single-particle occupations").
+    """
+    ms = b.ms
+    ns = len(ms)
+    rho = dict(p=np.zeros((ns, ns)), n=np.zeros((ns, ns)))
+    g = np.asarray(g, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    for s, (pm, nm) in enumerate(b.states()):
+        xs = x[s]
+        if xs == 0.0:
+            continue
+        for sp, mask in (("p", pm), ("n", nm)):
+            for c in _occ(mask, ns):
+                for a in range(ns):
+                    if ms[a][2] != ms[c][2] or ms[a][3] != ms[c][3]:
+                        continue
+                    res = apply_ops(mask, [("+", a), ("-", c)])
+                    if res is None:
+                        continue
+                    t = b.index(res[1], nm) if sp == "p" else b.index(pm, res[1])
+                    rho[sp][a, c] += res[0] * g[t] * xs
+    return rho["p"], rho["n"]
+
+
 def jumps(b, species, src_subset=None):
     """Jump lists of one species over its kept SDs (or only from ``src_subset``).
 

@@ -479,3 +479,80 @@ def test_oracle_lanczos_full_krylov_recovers_spectrum():
     for k in range(5):
         r = H @ vecs5[k] - got5[k] * vecs5[k]
         assert np.linalg.norm(r) < 1e-6
+
+
+# ------------------------------------------ one-body transition densities
+def _random_pair(b, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(b.dim), rng.standard_normal(b.dim)
+
+
+@pytest.mark.parametrize("space,Z,N,two_M", [(inputs.SD_SHELL_LIKE, 2, 2, 0), (P_SHELL, 3, 2, 1)])
+def test_one_body_density_number_sum_rule(space, Z, N, two_M):
+    """sum_a p+_a p_a is the proton number operator: trace(rho_p) = Z <g,x>,
+    trace(rho_n) = N <g,x>."""
+    b = ob.build_basis(space, Z, N, two_M)
+    g, x = _random_pair(b, 5)
+    rp, rn = oh.one_body_densities(b, g, x)
+    assert abs(np.trace(rp) - Z * g @ x) < 1e-10 * np.abs(g) @ np.abs(x)
+    assert abs(np.trace(rn) - N * g @ x) < 1e-10 * np.abs(g) @ np.abs(x)
+
+
+def test_one_body_density_adjoint_and_selection_rule():
+    """(p+_a p_c)^T = p+_c p_a: rho(g, x)[a, c] = rho(x, g)[c, a]; entries that
+    change m or parity vanish."""
+    space = inputs.SD_SHELL_LIKE
+    b = ob.build_basis(space, 3, 2, 1)
+    g, x = _random_pair(b, 6)
+    rp, rn = oh.one_body_densities(b, g, x)
+    tp, tn = oh.one_body_densities(b, x, g)
+    assert np.max(np.abs(rp - tp.T)) < 1e-12 and np.max(np.abs(rn - tn.T)) < 1e-12
+    ms = b.ms
+    for a in range(len(ms)):
+        for c in range(len(ms)):
+            if ms[a][2] != ms[c][2]:
+                assert rp[a, c] == 0.0 and rn[a, c] == 0.0
+
+
+def test_one_body_density_of_a_single_determinant():
+    """For one basis state |S>: rho is diagonal with the occupations of S."""
+    space = inputs.SD_SHELL_LIKE
+    b = ob.build_basis(space, 2, 3, 1)
+    ns = len(b.ms)
+    for s in (0, b.dim // 2, b.dim - 1):
+        e = np.zeros(b.dim)
+        e[s] = 1.0
+        rp, rn = oh.one_body_densities(b, e, e)
+        pm, nm = b.states()[s]
+        assert np.array_equal(rp, np.diag([float((pm >> i) & 1) for i in range(ns)]))
+        assert np.array_equal(rn, np.diag([float((nm >> i) & 1) for i in range(ns)]))
+
+
+@pytest.mark.parametrize("space,Z,N,two_M", [(P_SHELL, 2, 2, 0), (inputs.SD_SHELL_LIKE, 2, 1, 1)])
+def test_one_body_density_matches_jordan_wigner(space, Z, N, two_M):
+    """rho against g^T (a+_a a_c) x with Jordan-Wigner matrices of each species."""
+    b = ob.build_basis(space, Z, N, two_M)
+    ns = len(b.ms)
+    a = jw.annihilators(ns)
+    ad = [m.T.tocsr() for m in a]
+    states = b.states()
+    pidx = np.array([s[0] for s in states])
+    nidx = np.array([s[1] for s in states])
+    g, x = _random_pair(b, 7)
+    rp, rn = oh.one_body_densities(b, g, x)
+    for aa in range(ns):
+        for cc in range(ns):
+            op = (ad[aa] @ a[cc]).tocsr()
+            mp = op[pidx][:, pidx].toarray() * (nidx[:, None] == nidx[None, :])
+            mn = op[nidx][:, nidx].toarray() * (pidx[:, None] == pidx[None, :])
+            assert abs(rp[aa, cc] - g @ mp @ x) < 1e-12
+            assert abs(rn[aa, cc] - g @ mn @ x) < 1e-12
+
+
+def test_one_body_density_c_matches_python():
+    space = inputs.SD_SHELL_LIKE
+    b = ob.build_basis(space, 3, 3, 0)
+    g, x = _random_pair(b, 8)
+    rp, rn = oh.one_body_densities(b, g, x)
+    cp, cn = of.one_body_densities(of.Prepared(b), g, x)
+    assert np.max(np.abs(rp - cp)) < 1e-12 and np.max(np.abs(rn - cn)) < 1e-12
