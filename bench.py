@@ -88,6 +88,40 @@ def cpu_baseline(w, x, seconds):
                        (r0, r0 + rows, o.dim, 100.0 * rows / o.dim, t))
 
 
+def density_leg(h, w, reps=5):
+    """Time the one-body transition densities of two float64 vectors; the
+    streamed bytes are the g and x rows (proton side) and columns (neutron
+    side) read once per jump of the class that keeps m and parity."""
+    import torch
+    from paper_1801_08432_amd import fotci, inputs
+    dev = "cuda:0"
+    g = torch.from_numpy(inputs.random_vector(h.dim, 1803)).to(dev)
+    x = torch.from_numpy(inputs.random_vector(h.dim, 1804)).to(dev)
+    h.one_body_density(g, x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        h.one_body_density(g, x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    two_m = np.concatenate([np.arange(-tj, tj + 1, 2) for tj in w["two_j"]])
+    ns = len(two_m)
+    sec = h.basis.export()["sectors"]
+    nbytes = 0
+    for kind, first_col, count_col, size_col, n_sd in ((fotci.JUMP_P1, 2, 3, 5, h.basis.n_psd),
+                                                       (fotci.JUMP_N1, 4, 5, 3, h.basis.n_nsd)):
+        sd_sec = np.full(n_sd, -1)
+        for si, row in enumerate(sec):
+            sd_sec[row[first_col]:row[first_col] + row[count_col]] = si
+        jj = h.jumps.export(kind)
+        keep = (two_m[jj[:, 3] // ns] == two_m[jj[:, 3] % ns]) & (sd_sec[jj[:, 1]] >= 0)
+        nbytes += int(np.sum(2 * 8 * sec[sd_sec[jj[keep, 1]], size_col]))
+    return dict(ms=round(1e3 * t, 4), streamed_bytes=nbytes, achieved_gbs=round(nbytes / t / 1e9, 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +132,7 @@ def main():
     ap.add_argument("--lanczos-iters", type=int, default=200)
     ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 1 GiB (float32) once, a known-size kernel for HBM counter calibration")
@@ -217,6 +252,8 @@ def main():
                               speedup_vs_f64_plain=round(res["f64_plain"][1] / res[mode][1], 3),
                               f64_tiled_rel_err_vs_plain=float(np.max(np.abs(res["f64"][0]["evals"] - e64) /
                                                                        np.abs(e64))))
+    if not a.no_density:
+        out["one_body_density"] = density_leg(h, w)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, xs, a.cpu_seconds)
     print(json.dumps(out), flush=True)

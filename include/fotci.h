@@ -162,6 +162,20 @@ int fotci_ham_upload(fotci_ham *h, void *dev_workspace, int64_t bytes, void *str
 int fotci_apply_H(const fotci_ham *h, int32_t mode, const void *x, void *y, void *stream);
 
 /*
+ * fotci_one_body_density -- m-scheme one-body transition densities of two
+ * vectors of the basis (Ch. 5, "One-body density matrices", in the
+ * proton-neutron form the reduced densities are coupled from):
+ *   rho_p[a*N_s + c] = <g| p+_a p_c |x>,  rho_n[a*N_s + c] = <g| n+_a n_c |x>.
+ * Only entries with equal 2m and parity of a and c can be nonzero. For
+ * g = x = psi (unit norm) the diagonals are the m-state occupations (Ch. 4,
+ * "Single-particle occupations"). g, x: device float64 [dim]; rho_p, rho_n:
+ * device float64 [N_s^2], overwritten; either may be NULL. Asynchronous on
+ * `stream`. FOTCI_ESTATE if the Hamiltonian is not uploaded.
+ */
+int fotci_one_body_density(const fotci_ham *h, const double *g, const double *x, double *rho_p, double *rho_n,
+                           void *stream);
+
+/*
  * fotci_apply_H_vjp -- adjoint of y = H(v) x for L = <g, y> (float64 only):
  *   dx = H g  (H is symmetric), written to dx (device, length dim) if non-NULL;
  *   d_v_pp[(ab),(cd)] += <g| p+_a p+_b p_d p_c |x>  (device [n_pairs^2]), and

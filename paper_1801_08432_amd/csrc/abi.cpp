@@ -183,6 +183,21 @@ int fotci_apply_H_vjp(const fotci_ham *h, const double *x, const double *g, doub
     });
 }
 
+int fotci_one_body_density(const fotci_ham *h, const double *g, const double *x, double *rho_p, double *rho_n,
+                           void *stream) {
+    return guard([&] {
+        if (!h || !x || !g) fail(FOTCI_EINVAL, "NULL argument");
+        if (!h->uploaded) fail(FOTCI_ESTATE, "Hamiltonian not uploaded");
+        const auto &cl = h->j->cls;
+        int q0 = -1;
+        for (int q = 0; q < cl.nq; ++q)
+            if (cl.delta[q] == 0 && cl.rho[q] == 1) q0 = q;
+        if (q0 < 0) fail(FOTCI_EINVAL, "no operator class conserves m and parity");
+        launch_one_body_density(h->dev, h->tc.sec_np, q0, g, x, rho_p, rho_n, stream);
+        return FOTCI_OK;
+    });
+}
+
 int64_t fotci_lanczos_workspace_bytes(const fotci_ham *h, const fotci_lanczos_opts *o) {
     int64_t r = 0;
     int rc = guard([&] {

@@ -251,6 +251,8 @@ void launch_apply_plain(const DevHam &d, int mode, const void *x, void *y, void 
 void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream,
                         void **events = nullptr);
 void build_tiled_tables(fotci_ham *h);
+void launch_one_body_density(const DevHam &d, const std::vector<int32_t> &h_sec_np, int q0, const double *g,
+                             const double *x, double *rho_p, double *rho_n, void *stream);
 void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g,
                 double *dx, double *d_spe_p, double *d_spe_n, double *d_v_pp, double *d_v_nn,
                 double *d_v_pn, void *stream);

@@ -13,6 +13,8 @@
 // Label bins receive float64 atomic adds (several jumps share a label).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fotci_internal.h"
 
 namespace fotci {
@@ -177,7 +179,96 @@ __global__ __launch_bounds__(kT) void k_vjp_pn(DevHam P, const double *__restric
     }
 }
 
+// One-body transition densities (Ch. 5, "One-body density matrices", before J
+// coupling): rho[a*ns + c] = <g| c+_a c_c |x>. Between vectors of one basis
+// only the operator class with no change of m and parity (q0) contributes,
+// so source and destination SDs share a basis sector: proton densities are
+// row dots g[row ip'] . x[row ip] per jump, neutron densities column dots.
+__global__ __launch_bounds__(kT) void k_obd_proton(DevHam P, int q0, const double *__restrict__ x,
+                                                   const double *__restrict__ g, double *rho) {
+    __shared__ double lds[kT / 64];
+    const int ip = blockIdx.x;
+    const int nq = P.nq;
+    const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q0], a1 = P.p.ob_ptr[(int64_t)ip * nq + q0 + 1];
+    if (a0 == a1) return;
+    const int nn = P.sec_nn[P.p_sector[ip]];
+    const int64_t base = P.p_pstart[ip];
+    const int32_t *ops = P.cls_ops + P.cls_off[q0];
+    for (int k = a0; k < a1; ++k) {
+        const int64_t sb = P.p_pstart[P.p.ob_src[k]];
+        double a = 0.0;
+        for (int c = threadIdx.x; c < nn; c += kT) a += g[base + c] * x[sb + c];
+        const double dot = block_sum_all(a, lds);
+        if (threadIdx.x == 0) {
+            const int code = P.p.ob_code[k];
+            atomicAdd(&rho[ops[code >> 1]], (code & 1) ? -dot : dot);
+        }
+    }
+}
+
+// Neutron side: thread = destination neutron SD jn' (a column of its basis
+// sector), block row = a chunk of kObdRows proton rows. Each thread keeps one
+// float64 accumulator per jump into its column (kObdJumps at a time) and
+// walks the rows: g[r, col] is read coalesced across the threads, the x
+// values it pairs with lie in the same row.
+constexpr int kObdRows = 64;
+constexpr int kObdJumps = 16;
+
+__global__ __launch_bounds__(kT) void k_obd_neutron(DevHam P, int q0, const double *__restrict__ x,
+                                                    const double *__restrict__ g, double *rho) {
+    const int jn = blockIdx.x * kT + threadIdx.x;
+    if (jn >= P.n.n_sd) return;
+    const int s = P.n_bsector[jn];
+    if (s < 0) return;
+    const int np = P.sec_np[s], nn = P.sec_nn[s];
+    const int r0 = blockIdx.y * kObdRows, r1 = min(np, r0 + kObdRows);
+    if (r0 >= r1) return;
+    const int nq = P.nq;
+    const int a0 = P.n.ob_ptr[(int64_t)jn * nq + q0], a1 = P.n.ob_ptr[(int64_t)jn * nq + q0 + 1];
+    const int64_t off = P.sec_off[s];
+    const int cd = P.n_local[jn];
+    const int32_t *ops = P.cls_ops + P.cls_off[q0];
+    for (int k0 = a0; k0 < a1; k0 += kObdJumps) {
+        const int kc = min(kObdJumps, a1 - k0);
+        int cs[kObdJumps];
+        double acc[kObdJumps];
+#pragma unroll
+        for (int k = 0; k < kObdJumps; ++k) {
+            cs[k] = k < kc ? P.n_local[P.n.ob_src[k0 + k]] : cd;
+            acc[k] = 0.0;
+        }
+        for (int r = r0; r < r1; ++r) {
+            const int64_t row = off + (int64_t)r * nn;
+            const double gv = g[row + cd];
+#pragma unroll
+            for (int k = 0; k < kObdJumps; ++k) acc[k] += gv * x[row + cs[k]];
+        }
+        for (int k = 0; k < kc; ++k) {
+            const int code = P.n.ob_code[k0 + k];
+            atomicAdd(&rho[ops[code >> 1]], (code & 1) ? -acc[k] : acc[k]);
+        }
+    }
+}
+
 }  // namespace
+
+void launch_one_body_density(const DevHam &d, const std::vector<int32_t> &h_sec_np, int q0, const double *g,
+                             const double *x, double *rho_p, double *rho_n, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int n2 = d.ns * d.ns;
+    if (rho_p) {
+        hipLaunchKernelGGL(k_zero, dim3((n2 + kT - 1) / kT), dim3(kT), 0, st, rho_p, n2);
+        hipLaunchKernelGGL(k_obd_proton, dim3(d.p.n_sd), dim3(kT), 0, st, d, q0, x, g, rho_p);
+    }
+    if (rho_n) {
+        hipLaunchKernelGGL(k_zero, dim3((n2 + kT - 1) / kT), dim3(kT), 0, st, rho_n, n2);
+        int max_np = 1;
+        for (int v : h_sec_np) max_np = std::max(max_np, v);
+        const dim3 grid((d.n.n_sd + kT - 1) / kT, (max_np + kObdRows - 1) / kObdRows);
+        hipLaunchKernelGGL(k_obd_neutron, grid, dim3(kT), 0, st, d, q0, x, g, rho_n);
+    }
+    hip_check(hipGetLastError(), "one-body density launch");
+}
 
 void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g, double *dx, double *d_spe_p,
                 double *d_spe_n, double *d_v_pp, double *d_v_nn, double *d_v_pn, void *stream) {

@@ -26,7 +26,8 @@ EXPORTED = [
     "fotci_last_error", "fotci_version", "fotci_build_basis", "fotci_free_basis", "fotci_basis_info",
     "fotci_basis_export", "fotci_build_jumps", "fotci_free_jumps", "fotci_jumps_count", "fotci_jumps_export",
     "fotci_set_interaction", "fotci_free_ham", "fotci_ham_set_values", "fotci_ham_workspace_bytes",
-    "fotci_ham_upload", "fotci_apply_H", "fotci_apply_H_vjp", "fotci_lanczos_workspace_bytes",
+    "fotci_ham_upload", "fotci_apply_H", "fotci_apply_H_vjp", "fotci_one_body_density",
+    "fotci_lanczos_workspace_bytes",
     "fotci_lanczos_lowest", "fotci_ham_op_counts", "fotci_ham_pn_work", "fotci_ham_set_pn_private_rows",
     "fotci_tridiag_eigh", "fotci_profile_start",
     "fotci_profile_stop",
@@ -74,6 +75,7 @@ def lib():
         "fotci_ham_upload": (ctypes.c_int, [P, P, I64, P]),
         "fotci_apply_H": (ctypes.c_int, [P, I32, P, P, P]),
         "fotci_apply_H_vjp": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P]),
+        "fotci_one_body_density": (ctypes.c_int, [P, P, P, P, P, P]),
         "fotci_lanczos_workspace_bytes": (I64, [P, P]),
         "fotci_lanczos_lowest": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P, P]),
         "fotci_ham_op_counts": (ctypes.c_int, [P, P, P, P, P]),
@@ -264,6 +266,16 @@ class Hamiltonian:
                                        _dev_ptr(grads["eps_n"]), _dev_ptr(grads["v_pp"]), _dev_ptr(grads["v_nn"]),
                                        _dev_ptr(grads["v_pn"]), _stream(stream)))
         return dx, grads
+
+    def one_body_density(self, g, x, stream=None):
+        """(rho_p, rho_n): device float64 [N_s, N_s] with rho[a, c] = <g| c+_a c_c |x>."""
+        import torch
+        ns = self.basis.n_states
+        rp = torch.empty(ns, ns, dtype=torch.float64, device=x.device)
+        rn = torch.empty_like(rp)
+        _check(lib().fotci_one_body_density(self._h, _dev_ptr(g), _dev_ptr(x), _dev_ptr(rp), _dev_ptr(rn),
+                                            _stream(stream)))
+        return rp, rn
 
     def lanczos_workspace_bytes(self, n_keep, n_iter, mode="f64", refine=True):
         o = LanczosOpts(n_keep, n_iter, MODES[mode] if isinstance(mode, str) else int(mode), int(refine))

@@ -193,3 +193,33 @@ def test_vjp_matches_oracle_densities():
             got = gr[k].cpu().numpy()
             want = ref["d_" + k]
             assert np.allclose(got, want, rtol=1e-11, atol=1e-11 * np.abs(want).max()), (name, k)
+
+
+@pytest.mark.parametrize("name", ["sd_2p2n", "sd_6p6n", "pf_4p4n"])
+def test_one_body_density_matches_oracle(name):
+    """m-scheme one-body transition densities against the oracle's direct
+    operator action (float64; ~10^3-10^6 terms per entry, 1e-12 relative)."""
+    w, h, o, prep = setup(name)
+    g = inputs.random_vector(h.dim, 21)
+    x = inputs.random_vector(h.dim, 22)
+    _say("[density]", name, h.dim)
+    rp, rn = h.one_body_density(torch.from_numpy(g).to(DEV), torch.from_numpy(x).to(DEV))
+    ep, en = of.one_body_densities(prep, g, x)
+    scale = np.abs(g) @ np.abs(x)
+    assert np.max(np.abs(rp.cpu().numpy() - ep)) <= 1e-12 * scale
+    assert np.max(np.abs(rn.cpu().numpy() - en)) <= 1e-12 * scale
+
+
+def test_occupations_of_the_ground_state():
+    """Ground state of sd_6p6n from float64 Lanczos: the density diagonals are
+    m-state occupations in [0, 1] summing to Z and N, and match the oracle."""
+    w, h, o, prep = setup("sd_6p6n")
+    piv = torch.from_numpy(inputs.random_vector(h.dim, 23)).to(DEV)
+    r = h.lanczos_lowest(piv, 1, 150, mode="f64", want_vectors=True)
+    psi = r["evecs"][0].contiguous()
+    rp, rn = h.one_body_density(psi, psi)
+    occ_p, occ_n = np.diag(rp.cpu().numpy()), np.diag(rn.cpu().numpy())
+    assert abs(occ_p.sum() - w["Z"]) < 1e-10 and abs(occ_n.sum() - w["N"]) < 1e-10
+    assert occ_p.min() > -1e-12 and occ_p.max() < 1 + 1e-12 and occ_n.min() > -1e-12 and occ_n.max() < 1 + 1e-12
+    ep, en = of.one_body_densities(prep, psi.cpu().numpy(), psi.cpu().numpy())
+    assert np.max(np.abs(rp.cpu().numpy() - ep)) < 1e-12 and np.max(np.abs(rn.cpu().numpy() - en)) < 1e-12
