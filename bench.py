@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--no-trlan", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 1 GiB (float32) once, a known-size kernel for HBM counter calibration")
@@ -252,6 +253,22 @@ def main():
                               speedup_vs_f64_plain=round(res["f64_plain"][1] / res[mode][1], 3),
                               f64_tiled_rel_err_vs_plain=float(np.max(np.abs(res["f64"][0]["evals"] - e64) /
                                                                        np.abs(e64))))
+    if not a.no_trlan:
+        piv = torch.from_numpy(inputs.random_vector(h.dim, 1802)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = h.lanczos_thick_restart(piv, 10, 30, 80, max_restarts=60, mode=mode, tol=1e-8)
+        t = time.perf_counter() - t0
+        tr = dict(mode=mode, n_keep=10, n_thick=30, n_basis=80, tol=1e-8, seconds=round(t, 2),
+                  restarts=r["restarts"], applies=r["applies"], converged=r["converged"],
+                  max_resid=float(r["resid"].max()), workspace_gb=round(r["workspace_bytes"] / 1e9, 2),
+                  standard_workspace_gb=round(h.lanczos_workspace_bytes(10, a.lanczos_iters, mode) / 1e9, 2))
+        if "lanczos" in out:
+            ref = res["f64_plain"][0]["evals"]
+            tr["lowest5_rel_diff_vs_standard_f64_plain"] = float(np.max(np.abs(r["evals"][:5] - ref[:5]) /
+                                                                       np.abs(ref[:5])))
+        out["thick_restart"] = tr
+        log("[bench] thick restart: %s" % tr)
     if not a.no_density:
         out["one_body_density"] = density_leg(h, w)
     if not a.no_cpu:

@@ -218,6 +218,43 @@ int fotci_lanczos_lowest(const fotci_ham *h, const fotci_lanczos_opts *o, const 
                          void *work, int64_t work_bytes, double *evals, double *resid,
                          double *evecs, double *alpha, double *beta, void *stream);
 
+/*
+ * Thick-restart Lanczos (Ch. 7, "Thick-restart Lanczos"): the basis is held
+ * to n_basis + 1 vectors. When a cycle has reached n_basis vectors, the
+ * projected matrix is diagonalised; unless the lowest n_keep Ritz pairs have
+ * converged (|beta_last L[last, mu]| <= tol * max(1, |E_mu|)), the n_thick
+ * lowest Ritz vectors and the last Lanczos vector start the next cycle.
+ * Every step reorthogonalises fully (classical Gram-Schmidt, twice, float64
+ * sums), vectors are stored in the mode's precision as in
+ * fotci_lanczos_lowest, and the final Ritz vectors are refined in float64.
+ */
+typedef struct {
+    int32_t n_keep;        /* lowest eigenpairs wanted, 1..16 */
+    int32_t n_thick;       /* Ritz vectors kept at a restart, n_keep <= n_thick */
+    int32_t n_basis;       /* Lanczos vectors per cycle, n_thick + 2 <= n_basis <= 4095 */
+    int32_t max_restarts;  /* restarts allowed (>= 0) */
+    int32_t mode;          /* FOTCI_MODE_* */
+    int32_t refine;        /* 1: float64 Rayleigh-quotient refinement of the Ritz vectors */
+    double tol;            /* convergence threshold (> 0) on the residual estimate */
+} fotci_trlan_opts;
+
+/* Bytes of device workspace fotci_lanczos_thick_restart needs (negative
+ * error code for invalid options). */
+int64_t fotci_trlan_workspace_bytes(const fotci_ham *h, const fotci_trlan_opts *o);
+
+/*
+ * pivot: device float64 [dim]; work: device workspace (256-byte aligned) of
+ * at least the queried size; evals, resid: host [n_keep]; evecs: device
+ * float64 [n_keep*dim] Ritz vectors or NULL; stats: host int32[3] =
+ * {restarts, apply_H calls in the cycles, converged (0/1)} or NULL. A run
+ * that exhausts max_restarts returns FOTCI_OK with stats[2] = 0 and the
+ * current Ritz pairs. Synchronous. FOTCI_ENOTCONV if the Krylov space breaks
+ * down before n_keep Ritz values exist.
+ */
+int fotci_lanczos_thick_restart(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, void *work,
+                                int64_t work_bytes, double *evals, double *resid, double *evecs, int32_t *stats,
+                                void *stream);
+
 /* Counts of the work in one apply_H (host; no device needed): multiply-adds
  * of the pp, nn and pn parts and of the diagonal, as the paper counts
  * "operations" (Ch. 8, "Jump storage"). */
@@ -260,6 +297,15 @@ int fotci_profile_stop(fotci_ham *h, double *avg_ms, const char **names, int32_t
  * evecs: host [n*n] row-major, column k = eigenvector k, or NULL.
  */
 int fotci_tridiag_eigh(int32_t n, const double *diag, const double *offdiag, double *evals, double *evecs);
+
+/*
+ * Host utility: eigenvalues (ascending) and orthonormal eigenvectors of a
+ * dense symmetric float64 matrix a[n*n] (row-major; FOTCI_EINVAL unless
+ * exactly symmetric), by cyclic Jacobi rotations -- the projected-matrix step
+ * of thick-restart Lanczos. evecs: host [n*n] row-major, column k =
+ * eigenvector k, or NULL.
+ */
+int fotci_sym_eigh(int32_t n, const double *a, double *evals, double *evecs);
 
 #ifdef __cplusplus
 }

@@ -220,6 +220,27 @@ int fotci_lanczos_lowest(const fotci_ham *h, const fotci_lanczos_opts *o, const 
     });
 }
 
+int64_t fotci_trlan_workspace_bytes(const fotci_ham *h, const fotci_trlan_opts *o) {
+    int64_t r = 0;
+    int rc = guard([&] {
+        if (!h || !o) fail(FOTCI_EINVAL, "NULL argument");
+        r = trlan_bytes(h, o);
+        return FOTCI_OK;
+    });
+    return rc == FOTCI_OK ? r : rc;
+}
+
+int fotci_lanczos_thick_restart(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, void *work,
+                                int64_t work_bytes, double *evals, double *resid, double *evecs, int32_t *stats,
+                                void *stream) {
+    return guard([&] {
+        if (!h || !o || !pivot || !work || !evals || !resid) fail(FOTCI_EINVAL, "NULL argument");
+        if (!h->uploaded) fail(FOTCI_ESTATE, "Hamiltonian not uploaded");
+        trlan_run(h, o, pivot, work, work_bytes, evals, resid, evecs, stats, stream);
+        return FOTCI_OK;
+    });
+}
+
 int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn, int64_t *ops_diag) {
     return guard([&] { return fotci_ham_op_counts_impl(h, ops_pp, ops_nn, ops_pn, ops_diag); });
 }
@@ -285,6 +306,20 @@ int fotci_tridiag_eigh(int32_t n, const double *diag, const double *offdiag, dou
         std::vector<double> d(diag, diag + n), e(n > 1 ? n - 1 : 0), z;
         for (int i = 0; i + 1 < n; ++i) e[i] = offdiag[i];
         tridiag_eig(n, d, e, z);
+        std::memcpy(evals, d.data(), (size_t)n * 8);
+        if (evecs) std::memcpy(evecs, z.data(), (size_t)n * n * 8);
+        return FOTCI_OK;
+    });
+}
+
+int fotci_sym_eigh(int32_t n, const double *a, double *evals, double *evecs) {
+    return guard([&] {
+        if (n < 1 || !a || !evals) fail(FOTCI_EINVAL, "bad argument");
+        std::vector<double> m(a, a + (size_t)n * n), d, z;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < i; ++j)
+                if (m[(size_t)i * n + j] != m[(size_t)j * n + i]) fail(FOTCI_EINVAL, "matrix not symmetric");
+        sym_eig(n, m, d, z);
         std::memcpy(evals, d.data(), (size_t)n * 8);
         if (evecs) std::memcpy(evecs, z.data(), (size_t)n * n * 8);
         return FOTCI_OK;

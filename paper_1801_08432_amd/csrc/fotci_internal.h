@@ -260,11 +260,17 @@ int64_t lanczos_bytes(const fotci_ham *h, const fotci_lanczos_opts *o);
 void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, void *work,
                  int64_t work_bytes, double *evals, double *resid, double *evecs, double *alpha,
                  double *beta, void *stream);
+int64_t trlan_bytes(const fotci_ham *h, const fotci_trlan_opts *o);
+void trlan_run(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, void *work, int64_t work_bytes,
+               double *evals, double *resid, double *evecs, int32_t *stats, void *stream);
 void hip_check(int err, const char *what);
 
 // tridiagonal symmetric eigenproblem (host, float64): implicit QL with
 // Wilkinson shifts; eigenvalues ascending in d, eigenvectors in z (n x n,
 // column k = eigenvector k, row-major storage z[i*n+k]).
 void tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, std::vector<double> &z);
+// dense symmetric eigenproblem (host, float64), cyclic Jacobi; a: n x n
+// row-major; same output layout as tridiag_eig
+void sym_eig(int n, std::vector<double> a, std::vector<double> &d, std::vector<double> &z);
 
 }  // namespace fotci

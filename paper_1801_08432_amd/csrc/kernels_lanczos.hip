@@ -295,20 +295,22 @@ __global__ __launch_bounds__(kThreads) void k_scale_store(const double *__restri
         out[i] = (T)(in[i] * s);
 }
 
-// Y_j[r] = sum_l V_l[r] S[l*nk + j] for j < nk (float64 accumulation)
-template <typename T>
+// Y_j[r] = sum_l V_l[r] S[l*s_ld + j0 + j] for j < nk <= 16 (float64
+// accumulation), stored as TO with row stride y_ld: the Ritz vectors, and the
+// new leading basis vectors at a thick restart.
+template <typename T, typename TO>
 __global__ __launch_bounds__(kThreads) void k_ritz(const T *__restrict__ V, int64_t ld, int k,
-                                                   const double *__restrict__ S, int nk, double *__restrict__ Y,
-                                                   int64_t n) {
+                                                   const double *__restrict__ S, int s_ld, int j0, int nk,
+                                                   TO *__restrict__ Y, int64_t y_ld, int64_t n) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
     double acc[16];
     for (int j = 0; j < nk; ++j) acc[j] = 0.0;
     for (int l = 0; l < k; ++l) {
         const double v = (double)V[(int64_t)l * ld + r];
-        for (int j = 0; j < nk; ++j) acc[j] += v * S[l * nk + j];
+        for (int j = 0; j < nk; ++j) acc[j] += v * S[l * s_ld + j0 + j];
     }
-    for (int j = 0; j < nk; ++j) Y[(int64_t)j * n + r] = acc[j];
+    for (int j = 0; j < nk; ++j) Y[(int64_t)j * y_ld + r] = (TO)acc[j];
 }
 
 // r = hy - theta y; partial sums of r^2
@@ -334,81 +336,113 @@ int chunk_blocks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 
 int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
+// Workspace of both drivers: nvec Lanczos vectors and nscr scratch vectors
+// in the storage precision (leading dimension ld), then float64 work vectors
+// and small arrays.
 struct Layout {
     int64_t ld;   // basis leading dimension (elements): dim rounded up to 64
-    int64_t basis, y, w, partial, scal, coef, S, ritz, hy, total;
+    int64_t basis, scratch, y, w, partial, scal, coef, S, ritz, hy, total;
 };
 
-Layout make_layout(const fotci_ham *h, const fotci_lanczos_opts *o) {
-    const int64_t dim = h->j->b->dim;
-    const int es = (o->mode == FOTCI_MODE_F64 || o->mode == FOTCI_MODE_F64_PLAIN) ? 8 : 4;
+Layout make_layout(int64_t dim, int es, int nvec, int nscr, int ncoef, int s_cols, int n_keep) {
     Layout L{};
     L.ld = (dim + 63) & ~(int64_t)63;
     int64_t off = 0;
     L.basis = off;
-    off = a256(off + (int64_t)o->n_iter * L.ld * es);
+    off = a256(off + (int64_t)nvec * L.ld * es);
+    L.scratch = off;
+    off = a256(off + (int64_t)nscr * L.ld * es);
     L.y = off;
     off = a256(off + dim * es);
     L.w = off;
     off = a256(off + dim * 8);
     const int64_t nb = std::max<int64_t>(chunk_blocks(dim), 2048);
     L.partial = off;
-    off = a256(off + (int64_t)std::max(o->n_iter, 1) * nb * 8);
+    off = a256(off + (int64_t)std::max(ncoef, 1) * nb * 8);
     L.scal = off;
     off = a256(off + 64 * 8);
     L.coef = off;
-    off = a256(off + (int64_t)o->n_iter * 8);
+    off = a256(off + (int64_t)ncoef * 8);
     L.S = off;
-    off = a256(off + (int64_t)o->n_iter * o->n_keep * 8);
+    off = a256(off + (int64_t)ncoef * s_cols * 8);
     L.ritz = off;
-    off = a256(off + (int64_t)o->n_keep * dim * 8);
+    off = a256(off + (int64_t)n_keep * dim * 8);
     L.hy = off;
     off = a256(off + dim * 8);
     L.total = off;
     return L;
 }
 
-template <typename T>
-void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, char *work, double *evals,
-         double *resid, double *evecs, double *alpha_out, double *beta_out, hipStream_t st) {
-    const int64_t dim = h->j->b->dim;
-    const Layout L = make_layout(h, o);
-    T *basis = (T *)(work + L.basis);
-    T *y = (T *)(work + L.y);
-    double *w = (double *)(work + L.w);
-    double *partial = (double *)(work + L.partial);
-    double *scal = (double *)(work + L.scal);   // [0]=alpha [1]=beta [2]=norm [3]=theta
-    double *coef = (double *)(work + L.coef);
-    double *Sd = (double *)(work + L.S);
-    double *ritz = evecs ? evecs : (double *)(work + L.ritz);
-    double *hy = (double *)(work + L.hy);
-    const int64_t ld = L.ld;
-    const int sb = stream_blocks(dim);
-    const int cb = chunk_blocks(dim);
-    const int mode = o->mode;
-    const int hi_mode = (mode == FOTCI_MODE_F64_PLAIN) ? FOTCI_MODE_F64_PLAIN : FOTCI_MODE_F64;
+int elem_size(int mode) { return (mode == FOTCI_MODE_F64 || mode == FOTCI_MODE_F64_PLAIN) ? 8 : 4; }
 
-    auto dot_into = [&](auto *a, auto *b, double *out, int take_sqrt) {
-        hipLaunchKernelGGL((k_dot_partial<std::remove_cv_t<std::remove_pointer_t<decltype(a)>>,
-                                          std::remove_cv_t<std::remove_pointer_t<decltype(b)>>>),
-                           dim3(sb), dim3(kThreads), 0, st, a, b, dim, partial);
+Layout standard_layout(const fotci_ham *h, const fotci_lanczos_opts *o) {
+    return make_layout(h->j->b->dim, elem_size(o->mode), o->n_iter, 0, o->n_iter, o->n_keep, o->n_keep);
+}
+
+// Thick restart: n_basis + 1 vectors, n_thick scratch vectors.
+Layout trlan_layout(const fotci_ham *h, const fotci_trlan_opts *o) {
+    return make_layout(h->j->b->dim, elem_size(o->mode), o->n_basis + 1, o->n_thick, o->n_basis + 1,
+                       std::max(o->n_thick, o->n_keep), o->n_keep);
+}
+
+// Device state and the steps shared by the standard and thick-restart drivers.
+template <typename T>
+struct Lz {
+    const fotci_ham *h;
+    hipStream_t st;
+    int64_t dim, ld;
+    int sb, cb, mode, hi_mode;
+    T *basis, *scratch, *y;
+    double *w, *partial, *scal, *coef, *Sd, *ritz, *hy;   // scal: [0] alpha [1] beta [2] norm [3] theta [4] resid
+
+    Lz(const fotci_ham *h_, const Layout &L, int mode_, char *work, double *evecs, hipStream_t st_)
+        : h(h_), st(st_), dim(h_->j->b->dim), ld(L.ld), sb(stream_blocks(dim)), cb(chunk_blocks(dim)),
+          mode(mode_), hi_mode(mode_ == FOTCI_MODE_F64_PLAIN ? FOTCI_MODE_F64_PLAIN : FOTCI_MODE_F64) {
+        basis = (T *)(work + L.basis);
+        scratch = (T *)(work + L.scratch);
+        y = (T *)(work + L.y);
+        w = (double *)(work + L.w);
+        partial = (double *)(work + L.partial);
+        scal = (double *)(work + L.scal);
+        coef = (double *)(work + L.coef);
+        Sd = (double *)(work + L.S);
+        ritz = evecs ? evecs : (double *)(work + L.ritz);
+        hy = (double *)(work + L.hy);
+    }
+
+    T *vec(int i) const { return basis + (int64_t)i * ld; }
+
+    template <typename A, typename B>
+    void dot_into(const A *a, const B *b, double *out, int take_sqrt) {
+        hipLaunchKernelGGL((k_dot_partial<A, B>), dim3(sb), dim3(kThreads), 0, st, a, b, dim, partial);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, sb, out, take_sqrt);
-    };
+    }
 
     // v_0 = pivot / ||pivot||
-    dot_into(pivot, pivot, scal + 2, 1);
-    hipLaunchKernelGGL(k_scale_store<T>, dim3(sb), dim3(kThreads), 0, st, pivot, (const double *)(scal + 2), basis,
-                       dim);
-    std::vector<double> al, be;
-    double tnorm = 0.0;
-    int k = 0;
-    for (int i = 0; i < o->n_iter; ++i) {
-        T *vi = basis + (int64_t)i * ld;
+    void start(const double *pivot) {
+        dot_into(pivot, pivot, scal + 2, 1);
+        hipLaunchKernelGGL(k_scale_store<T>, dim3(sb), dim3(kThreads), 0, st, pivot, (const double *)(scal + 2),
+                           basis, dim);
+    }
+
+    // One Lanczos step on v_i (Ch. 7, "Standard Lanczos algorithm"): y = H v_i,
+    // alpha = <v_i, y>, w = y - alpha v_i - (beta v_{i-1} when three_term; the
+    // arrow terms sum_mu s_mu v_mu, mu < n_arrow, after a thick restart), then
+    // classical Gram-Schmidt twice against v_0..v_i and beta = ||w||.
+    // Returns alpha and beta on the host.
+    void step(int i, bool three_term, const std::vector<double> &arrow, double &alpha, double &beta) {
+        T *vi = vec(i);
         launch_apply(h, mode, vi, y, st);
         dot_into((const T *)vi, (const T *)y, scal + 0, 0);
         hipLaunchKernelGGL(k_three_term<T>, dim3(sb), dim3(kThreads), 0, st, (const T *)y, (const T *)vi,
-                           (const T *)(i > 0 ? vi - ld : nullptr), (const double *)(scal + 0),
+                           (const T *)(three_term && i > 0 ? vi - ld : nullptr), (const double *)(scal + 0),
                            (const double *)(scal + 1), w, dim);
+        if (!arrow.empty()) {
+            const int na = (int)arrow.size();
+            hip_check(hipMemcpyAsync(coef, arrow.data(), (size_t)na * 8, hipMemcpyHostToDevice, st), "arrow copy");
+            hipLaunchKernelGGL(k_subtract<T>, dim3(cb), dim3(kThreads), (size_t)(na + kWaves) * 8, st,
+                               (const T *)basis, ld, na, (const double *)coef, w, dim, (double *)nullptr);
+        }
         for (int pass = 0; pass < 2; ++pass) {
             hipLaunchKernelGGL(k_multidot<T>, dim3(cb), dim3(kThreads), 0, st, (const T *)basis, ld, i + 1,
                                (const double *)w, dim, partial);
@@ -423,61 +457,178 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
         double ab[2];
         hip_check(hipMemcpyAsync(ab, scal, 16, hipMemcpyDeviceToHost, st), "lanczos copy");
         hip_check(hipStreamSynchronize(st), "lanczos sync");
-        al.push_back(ab[0]);
-        k = i + 1;
-        tnorm = std::max(tnorm, std::fabs(ab[0]) + ab[1] + (be.empty() ? 0.0 : be.back()));
-        if (i == o->n_iter - 1) {
-            be.push_back(ab[1]);
-            break;
-        }
-        be.push_back(ab[1]);
-        if (!(ab[1] > 1e-12 * tnorm)) break;   // invariant subspace reached
+        alpha = ab[0];
+        beta = ab[1];
+    }
+
+    // v_{i+1} = w / beta (beta in scal[1] from the last step)
+    void store_next(int i) {
         hipLaunchKernelGGL(k_scale_store<T>, dim3(sb), dim3(kThreads), 0, st, (const double *)w,
-                           (const double *)(scal + 1), basis + (int64_t)(i + 1) * ld, dim);
+                           (const double *)(scal + 1), vec(i + 1), dim);
+    }
+
+    // out_j = sum_{l<m} v_l Z[l, j0 + j] for j < nk, in chunks of 16 columns;
+    // Z: host m x zc row-major.
+    template <typename TO>
+    void combine(int m, const std::vector<double> &Z, int zc, int nk, TO *out, int64_t out_ld) {
+        hip_check(hipMemcpyAsync(Sd, Z.data(), (size_t)m * zc * 8, hipMemcpyHostToDevice, st), "coefficient copy");
+        for (int j0 = 0; j0 < nk; j0 += 16) {
+            const int nc = std::min(16, nk - j0);
+            hipLaunchKernelGGL((k_ritz<T, TO>), dim3((int)((dim + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                               (const T *)basis, ld, m, (const double *)Sd, zc, j0, nc, out + (int64_t)j0 * out_ld,
+                               out_ld, dim);
+        }
+        hip_check(hipGetLastError(), "combine launch");
+    }
+
+    // Ritz vectors of the lowest nk eigenpairs (theta ascending, columns of z,
+    // m x m row-major) in float64, normalised; with refine, theta becomes the
+    // float64 Rayleigh quotient; resid = ||H y - theta y||.
+    void ritz_pairs(int m, const std::vector<double> &theta, const std::vector<double> &z, int nk, bool refine,
+                    double *evals, double *resid) {
+        std::vector<double> S((size_t)m * nk);
+        for (int l = 0; l < m; ++l)
+            for (int j = 0; j < nk; ++j) S[(size_t)l * nk + j] = z[(size_t)l * m + j];
+        combine<double>(m, S, nk, nk, ritz, dim);
+        for (int j = 0; j < nk; ++j) {
+            double *yj = ritz + (int64_t)j * dim;
+            dot_into((const double *)yj, (const double *)yj, scal + 2, 1);
+            hipLaunchKernelGGL(k_scale_store<double>, dim3(sb), dim3(kThreads), 0, st, (const double *)yj,
+                               (const double *)(scal + 2), yj, dim);
+            launch_apply(h, hi_mode, yj, hy, st);
+            if (refine) {
+                dot_into((const double *)yj, (const double *)hy, scal + 3, 0);
+            } else {
+                hip_check(hipMemcpyAsync(scal + 3, &theta[j], 8, hipMemcpyHostToDevice, st), "theta copy");
+            }
+            hipLaunchKernelGGL(k_resid_partial, dim3(sb), dim3(kThreads), 0, st, (const double *)hy,
+                               (const double *)yj, (const double *)(scal + 3), dim, partial);
+            hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, sb, scal + 4, 1);
+            double tr[2];
+            hip_check(hipMemcpyAsync(tr, scal + 3, 16, hipMemcpyDeviceToHost, st), "ritz copy");
+            hip_check(hipStreamSynchronize(st), "ritz sync");
+            evals[j] = tr[0];
+            resid[j] = tr[1];
+        }
+        hip_check(hipGetLastError(), "ritz launch");
+    }
+};
+
+template <typename T>
+void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, char *work, double *evals,
+         double *resid, double *evecs, double *alpha_out, double *beta_out, hipStream_t st) {
+    Lz<T> z(h, standard_layout(h, o), o->mode, work, evecs, st);
+    z.start(pivot);
+    std::vector<double> al, be;
+    const std::vector<double> none;
+    double tnorm = 0.0;
+    int k = 0;
+    for (int i = 0; i < o->n_iter; ++i) {
+        double a, b;
+        z.step(i, true, none, a, b);
+        al.push_back(a);
+        be.push_back(b);
+        k = i + 1;
+        tnorm = std::max(tnorm, std::fabs(a) + b + (i > 0 ? be[i - 1] : 0.0));
+        if (i == o->n_iter - 1) break;
+        if (!(b > 1e-12 * tnorm)) break;   // invariant subspace reached
+        z.store_next(i);
     }
     if (alpha_out)
         for (int i = 0; i < o->n_iter; ++i) alpha_out[i] = i < k ? al[i] : 0.0;
     if (beta_out)
         for (int i = 0; i < o->n_iter; ++i) beta_out[i] = i < (int)be.size() ? be[i] : 0.0;
     if (k < o->n_keep) fail(FOTCI_ENOTCONV, "Krylov space smaller than n_keep");
-    // tridiagonal eigenproblem
-    std::vector<double> d(al.begin(), al.begin() + k), e(k > 1 ? k - 1 : 0), z;
+    std::vector<double> d(al.begin(), al.begin() + k), e(k > 1 ? k - 1 : 0), zz;
     for (int i = 0; i + 1 < k; ++i) e[i] = be[i];
-    tridiag_eig(k, d, e, z);
-    const int nk = o->n_keep;
-    std::vector<double> S((size_t)k * nk);
-    for (int l = 0; l < k; ++l)
-        for (int j = 0; j < nk; ++j) S[(size_t)l * nk + j] = z[(size_t)l * k + j];
-    hip_check(hipMemcpyAsync(Sd, S.data(), S.size() * 8, hipMemcpyHostToDevice, st), "ritz copy");
-    hipLaunchKernelGGL(k_ritz<T>, dim3((int)((dim + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
-                       (const T *)basis, ld, k, (const double *)Sd, nk, ritz, dim);
-    for (int j = 0; j < nk; ++j) {
-        double *yj = ritz + (int64_t)j * dim;
-        // normalise the Ritz vector in float64
-        dot_into((const double *)yj, (const double *)yj, scal + 2, 1);
-        hipLaunchKernelGGL(k_scale_store<double>, dim3(sb), dim3(kThreads), 0, st, (const double *)yj,
-                           (const double *)(scal + 2), yj, dim);
-        launch_apply(h, hi_mode, yj, hy, st);
-        if (o->refine) {
-            dot_into((const double *)yj, (const double *)hy, scal + 3, 0);
-        } else {
-            hip_check(hipMemcpyAsync(scal + 3, &d[j], 8, hipMemcpyHostToDevice, st), "theta copy");
+    tridiag_eig(k, d, e, zz);
+    z.ritz_pairs(k, d, zz, o->n_keep, o->refine != 0, evals, resid);
+}
+
+// Thick-restart Lanczos (Ch. 7, "Thick-restart Lanczos"). Each cycle extends
+// the basis to n_basis + 1 vectors; the projected matrix T of the first
+// n_basis vectors is diagonalised on the host; if the lowest n_keep Ritz
+// pairs are not converged (|beta_last L[last, mu]| <= tol max(1, |E_mu|)),
+// the n_thick lowest Ritz vectors become v_0..v_{nt-1}, the last Lanczos
+// vector becomes v_nt, and T restarts as diag(E_mu) with the arrow column
+// s_mu = beta_last L[last, mu] coupling them to v_nt. The first step after a
+// restart subtracts the arrow terms instead of the three-term recurrence.
+template <typename T>
+void run_trlan(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, char *work, double *evals,
+               double *resid, double *evecs, int32_t *stats, hipStream_t st) {
+    const Layout L = trlan_layout(h, o);
+    Lz<T> z(h, L, o->mode, work, evecs, st);
+    const int kb = o->n_basis, nt = o->n_thick;
+    z.start(pivot);
+    std::vector<double> Tm((size_t)(kb + 1) * (kb + 1), 0.0);
+    auto TT = [&](int i, int j) -> double & { return Tm[(size_t)i * (kb + 1) + j]; };
+    std::vector<double> arrow;
+    int j0 = 0, restarts = 0, applies = 0, converged = 0;
+    double tnorm = 0.0;
+    std::vector<double> theta, Z;
+    int m = 0;
+    for (;;) {
+        m = kb;
+        bool breakdown = false;
+        for (int i = j0; i < kb; ++i) {
+            double a, b;
+            z.step(i, i > j0 || j0 == 0, i == j0 ? arrow : std::vector<double>(), a, b);
+            ++applies;
+            TT(i, i) = a;
+            TT(i, i + 1) = TT(i + 1, i) = b;
+            double row = std::fabs(a) + b;
+            for (int j = 0; j < i; ++j) row += std::fabs(TT(i, j));
+            tnorm = std::max(tnorm, row);
+            if (!(b > 1e-12 * tnorm)) {   // invariant subspace: the Ritz pairs so far are exact
+                m = i + 1;
+                breakdown = true;
+                break;
+            }
+            z.store_next(i);
         }
-        hipLaunchKernelGGL(k_resid_partial, dim3(sb), dim3(kThreads), 0, st, (const double *)hy, (const double *)yj,
-                           (const double *)(scal + 3), dim, partial);
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, sb, scal + 4, 1);
-        double tr[2];
-        hip_check(hipMemcpyAsync(tr, scal + 3, 16, hipMemcpyDeviceToHost, st), "ritz copy");
-        hip_check(hipStreamSynchronize(st), "ritz sync");
-        evals[j] = tr[0];
-        resid[j] = tr[1];
+        std::vector<double> A((size_t)m * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = TT(i, j);
+        sym_eig(m, A, theta, Z);
+        const double blast = TT(m - 1, m);
+        converged = 1;
+        for (int mu = 0; mu < std::min(o->n_keep, m); ++mu)
+            if (!(std::fabs(blast * Z[(size_t)(m - 1) * m + mu]) <= o->tol * std::max(1.0, std::fabs(theta[mu]))))
+                converged = 0;
+        if (breakdown) converged = m >= o->n_keep ? 1 : 0;
+        if (converged || breakdown || restarts >= o->max_restarts) break;
+        // restart: v'_mu = sum_i v_i Z[i, mu] for mu < nt (float64 sums, stored in the
+        // basis precision), then v_m -> v_nt
+        std::vector<double> Zt((size_t)m * nt);
+        for (int i = 0; i < m; ++i)
+            for (int mu = 0; mu < nt; ++mu) Zt[(size_t)i * nt + mu] = Z[(size_t)i * m + mu];
+        z.template combine<T>(m, Zt, nt, nt, z.scratch, z.ld);
+        hip_check(hipMemcpyAsync(z.basis, z.scratch, (size_t)nt * z.ld * sizeof(T), hipMemcpyDeviceToDevice, st),
+                  "restart copy");
+        hip_check(hipMemcpyAsync(z.vec(nt), z.vec(m), (size_t)z.dim * sizeof(T), hipMemcpyDeviceToDevice, st),
+                  "restart copy");
+        std::fill(Tm.begin(), Tm.end(), 0.0);
+        arrow.assign(nt, 0.0);
+        for (int mu = 0; mu < nt; ++mu) {
+            TT(mu, mu) = theta[mu];
+            arrow[mu] = blast * Z[(size_t)(m - 1) * m + mu];
+            TT(mu, nt) = TT(nt, mu) = arrow[mu];
+        }
+        j0 = nt;
+        ++restarts;
     }
-    hip_check(hipGetLastError(), "ritz launch");
+    if (m < o->n_keep) fail(FOTCI_ENOTCONV, "Krylov space smaller than n_keep");
+    z.ritz_pairs(m, theta, Z, o->n_keep, o->refine != 0, evals, resid);
+    if (stats) {
+        stats[0] = restarts;
+        stats[1] = applies;
+        stats[2] = converged;
+    }
 }
 
 }  // namespace
 
-int64_t lanczos_bytes(const fotci_ham *h, const fotci_lanczos_opts *o) { return make_layout(h, o).total; }
+int64_t lanczos_bytes(const fotci_ham *h, const fotci_lanczos_opts *o) { return standard_layout(h, o).total; }
 
 void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, void *work, int64_t work_bytes,
                  double *evals, double *resid, double *evecs, double *alpha, double *beta, void *stream) {
@@ -497,6 +648,34 @@ void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *
         default:
             fail(FOTCI_EINVAL, "unknown mode");
     }
+}
+
+void check_trlan_opts(const fotci_trlan_opts *o) {
+    if (o->n_keep < 1 || o->n_keep > 16) fail(FOTCI_EINVAL, "n_keep must be in 1..16");
+    if (o->n_thick < o->n_keep) fail(FOTCI_EINVAL, "n_thick must be at least n_keep");
+    if (o->n_basis < o->n_thick + 2 || o->n_basis + 1 > kMaxIter)
+        fail(FOTCI_EINVAL, "n_basis must be in n_thick+2..4095");
+    if (o->max_restarts < 0) fail(FOTCI_EINVAL, "max_restarts must be >= 0");
+    if (!(o->tol > 0.0)) fail(FOTCI_EINVAL, "tol must be positive");
+    if (o->mode != FOTCI_MODE_F64 && o->mode != FOTCI_MODE_F64_PLAIN && o->mode != FOTCI_MODE_F32)
+        fail(FOTCI_EINVAL, "unknown mode");
+}
+
+int64_t trlan_bytes(const fotci_ham *h, const fotci_trlan_opts *o) {
+    check_trlan_opts(o);
+    return trlan_layout(h, o).total;
+}
+
+void trlan_run(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, void *work, int64_t work_bytes,
+               double *evals, double *resid, double *evecs, int32_t *stats, void *stream) {
+    check_trlan_opts(o);
+    if (work_bytes < trlan_bytes(h, o)) fail(FOTCI_ENOMEM, "Lanczos workspace too small");
+    if (((uintptr_t)work & 255u) != 0) fail(FOTCI_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    if (o->mode == FOTCI_MODE_F32)
+        run_trlan<float>(h, o, pivot, (char *)work, evals, resid, evecs, stats, st);
+    else
+        run_trlan<double>(h, o, pivot, (char *)work, evals, resid, evecs, stats, st);
 }
 
 }  // namespace fotci

@@ -28,8 +28,9 @@ EXPORTED = [
     "fotci_set_interaction", "fotci_free_ham", "fotci_ham_set_values", "fotci_ham_workspace_bytes",
     "fotci_ham_upload", "fotci_apply_H", "fotci_apply_H_vjp", "fotci_one_body_density",
     "fotci_lanczos_workspace_bytes",
-    "fotci_lanczos_lowest", "fotci_ham_op_counts", "fotci_ham_pn_work", "fotci_ham_set_pn_private_rows",
-    "fotci_tridiag_eigh", "fotci_profile_start",
+    "fotci_lanczos_lowest", "fotci_trlan_workspace_bytes", "fotci_lanczos_thick_restart",
+    "fotci_ham_op_counts", "fotci_ham_pn_work", "fotci_ham_set_pn_private_rows",
+    "fotci_tridiag_eigh", "fotci_sym_eigh", "fotci_profile_start",
     "fotci_profile_stop",
 ]
 
@@ -43,6 +44,12 @@ class FotciError(RuntimeError):
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("n_keep", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("refine", ctypes.c_int32)]
+
+
+class TrlanOpts(ctypes.Structure):
+    _fields_ = [("n_keep", ctypes.c_int32), ("n_thick", ctypes.c_int32), ("n_basis", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32), ("mode", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
 
 
 _lib = None
@@ -78,10 +85,13 @@ def lib():
         "fotci_one_body_density": (ctypes.c_int, [P, P, P, P, P, P]),
         "fotci_lanczos_workspace_bytes": (I64, [P, P]),
         "fotci_lanczos_lowest": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P, P]),
+        "fotci_trlan_workspace_bytes": (I64, [P, P]),
+        "fotci_lanczos_thick_restart": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P]),
         "fotci_ham_op_counts": (ctypes.c_int, [P, P, P, P, P]),
         "fotci_ham_pn_work": (ctypes.c_int, [P, P, P, P]),
         "fotci_ham_set_pn_private_rows": (ctypes.c_int, [P, ctypes.c_int32]),
         "fotci_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
+        "fotci_sym_eigh": (ctypes.c_int, [I32, P, P, P]),
         "fotci_profile_start": (ctypes.c_int, [P, I32]),
         "fotci_profile_stop": (ctypes.c_int, [P, P, P, P, P]),
     }
@@ -310,6 +320,40 @@ class Hamiltonian:
             out["evecs"] = evecs
         return out
 
+    def lanczos_thick_restart(self, pivot, n_keep, n_thick, n_basis, max_restarts=50, mode="f64", refine=True,
+                              tol=1e-10, want_vectors=False, stream=None):
+        """Thick-restart Lanczos; returns dict(evals, resid, restarts, applies, converged[, evecs])."""
+        import torch
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        o = TrlanOpts(n_keep, n_thick, n_basis, max_restarts, m, int(refine), float(tol))
+        nbytes = lib().fotci_trlan_workspace_bytes(self._h, ctypes.byref(o))
+        if nbytes < 0:
+            _check(int(nbytes))
+        if pivot.dtype != torch.float64 or pivot.numel() != self.dim or not pivot.is_contiguous():
+            raise ValueError("pivot must be a contiguous float64 device vector of length dim")
+        work = torch.empty(nbytes + 256, dtype=torch.uint8, device=pivot.device)
+        wptr = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        evals = np.zeros(n_keep)
+        resid = np.zeros(n_keep)
+        stats = np.zeros(3, dtype=np.int32)
+        evecs = torch.empty(n_keep, self.dim, dtype=torch.float64, device=pivot.device) if want_vectors else None
+        _check(lib().fotci_lanczos_thick_restart(self._h, ctypes.byref(o), _dev_ptr(pivot), wptr, nbytes,
+                                                 _np_ptr(evals), _np_ptr(resid), _dev_ptr(evecs), _np_ptr(stats),
+                                                 _stream(stream)))
+        out = dict(evals=evals, resid=resid, restarts=int(stats[0]), applies=int(stats[1]),
+                   converged=bool(stats[2]), workspace_bytes=int(nbytes))
+        if want_vectors:
+            out["evecs"] = evecs
+        return out
+
+    def trlan_workspace_bytes(self, n_keep, n_thick, n_basis, mode="f64", max_restarts=50, tol=1e-10):
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        o = TrlanOpts(n_keep, n_thick, n_basis, max_restarts, m, 1, float(tol))
+        n = lib().fotci_trlan_workspace_bytes(self._h, ctypes.byref(o))
+        if n < 0:
+            _check(int(n))
+        return int(n)
+
     def profile_start(self, max_calls):
         """Record HIP events around each apply_H kernel for up to max_calls calls."""
         _check(lib().fotci_profile_start(self._h, int(max_calls)))
@@ -326,6 +370,16 @@ class Hamiltonian:
         if getattr(self, "_h", None) is not None and _lib is not None:
             _lib.fotci_free_ham(self._h)
             self._h = None
+
+
+def sym_eigh(a):
+    """Host float64 dense symmetric eigensolver of the library (cyclic Jacobi)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    ev = np.zeros(n)
+    vec = np.zeros((n, n))
+    _check(lib().fotci_sym_eigh(n, _np_ptr(a), _np_ptr(ev), _np_ptr(vec)))
+    return ev, vec
 
 
 def tridiag_eigh(diag, offdiag):

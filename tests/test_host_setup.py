@@ -222,3 +222,37 @@ def test_pn_private_rows_argument():
     with pytest.raises(fotci.FotciError) as ei:
         fotci._check(fotci.lib().fotci_ham_set_pn_private_rows(h._h, 2))
     assert ei.value.code == -1   # FOTCI_EINVAL
+
+
+def test_dense_symmetric_solver_matches_numpy():
+    """The Jacobi solver of thick-restart Lanczos: a random symmetric matrix
+    and the restart shape (diagonal block, arrow column, tridiagonal tail)."""
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((40, 40))
+    a = a + a.T
+    b = np.zeros((30, 30))
+    b[np.arange(12), np.arange(12)] = np.sort(rng.standard_normal(12))
+    b[:12, 12] = b[12, :12] = rng.standard_normal(12)
+    for i in range(12, 30):
+        b[i, i] = rng.standard_normal()
+        if i + 1 < 30:
+            b[i, i + 1] = b[i + 1, i] = abs(rng.standard_normal())
+    for m in (a, b):
+        ev, vec = fotci.sym_eigh(m)
+        ref = np.linalg.eigvalsh(m)
+        assert np.max(np.abs(ev - ref)) < 1e-12 * np.max(np.abs(ref))
+        assert np.max(np.abs(vec.T @ vec - np.eye(len(m)))) < 1e-12
+        assert np.max(np.abs(m @ vec - vec * ev)) < 1e-11 * np.max(np.abs(ref))
+    with pytest.raises(fotci.FotciError):
+        fotci.sym_eigh(np.array([[1.0, 2.0], [3.0, 1.0]]))
+
+
+def test_thick_restart_options_are_checked():
+    w = inputs.WORKLOADS["sd_2p2n"]
+    inter, _ = inputs.random_interaction(w["two_j"], 3)
+    h = fotci.Hamiltonian.build(w["two_j"], w["Z"], w["N"], w["two_M"], inter, upload=False)
+    assert h.trlan_workspace_bytes(5, 10, 20) > 0
+    for bad in [dict(n_keep=5, n_thick=4, n_basis=20), dict(n_keep=5, n_thick=10, n_basis=11),
+                dict(n_keep=0, n_thick=10, n_basis=20), dict(n_keep=5, n_thick=10, n_basis=20, tol=0.0)]:
+        with pytest.raises(fotci.FotciError):
+            h.trlan_workspace_bytes(**bad)
