@@ -117,7 +117,7 @@ int fotci_jumps_export(const fotci_jumps *j, int32_t kind, int32_t *src, int32_t
 
 /*
  * fotci_set_interaction -- the one- plus two-body Hamiltonian in M-scheme
- * form (Ch. 11, "The Hamiltonian and other operators in second
+ * form (App. A, "The Hamiltonian and other operators in second
  * quantization", eq. hamdef, with V already uncoupled):
  *   H = sum_i eps_p[orb i] n_i(p) + sum_i eps_n[orb i] n_i(n)
  *     + sum_{a<b,c<d} v_pp[(ab),(cd)] p+_a p+_b p_d p_c   (v_nn alike)

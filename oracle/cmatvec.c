@@ -10,7 +10,7 @@
  *     + sum_{abcd} V_pn[(a b),(c d)] (p+_a p_c)(n+_b n_d)
  *
  * (the M-scheme form of the standard one- plus two-body Hamiltonian, eq.
- * hamdef of Ch. 11), acting on occupation bit strings with the fermion sign
+ * hamdef of App. A), acting on occupation bit strings with the fermion sign
  * (-1)^(occupied states of lower index) (Ch. 2, "Representation of the
  * basis"). The basis is the factorised proton x neutron one: index =
  * pstart(ip) + nstart(jn) (Ch. 2 "factorization of the basis", Ch. 6 ".bas"

@@ -1,7 +1,7 @@
 """Direct second-quantised action of the one- plus two-body Hamiltonian.
 
 The Hamiltonian is the M-scheme form of the paper's standard one- plus
-two-body operator (Ch. 11, "The Hamiltonian and other operators in second
+two-body operator (App. A, "The Hamiltonian and other operators in second
 quantization", eq. hamdef), with the proton-neutron part written on product
 states (Ch. 2, "Representation of the Hamiltonian": pp and nn forces act on
 one species with the other a spectator, pn forces act on both):
