@@ -237,13 +237,14 @@ def main():
     if not a.no_lanczos:
         piv = torch.from_numpy(inputs.random_vector(h.dim, 1802)).to(dev)
         res = {}
-        for m in (mode, "f64", "f64_plain"):
+        for m, ro in ((mode, "cgs2"), ("f64", "cgs2"), ("f64_plain", "cgs2"), (mode, "dgks")):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = h.lanczos_lowest(piv, 10, a.lanczos_iters, mode=m)
+            r = h.lanczos_lowest(piv, 10, a.lanczos_iters, mode=m, reorth=ro)
             t = time.perf_counter() - t0
-            res[m] = (r, t)
-            log("[bench] lanczos %s: %.2f s, evals %s" % (m, t, np.array2string(r["evals"][:3])))
+            key = m if ro == "cgs2" else m + "_dgks"
+            res[key] = (r, t)
+            log("[bench] lanczos %s: %.2f s, evals %s" % (key, t, np.array2string(r["evals"][:3])))
         e32, e64 = res[mode][0]["evals"], res["f64_plain"][0]["evals"]
         rel = np.abs(e32 - e64) / np.abs(e64)
         out["lanczos"] = dict(n_iter=a.lanczos_iters, n_keep=10,
@@ -252,7 +253,11 @@ def main():
                               max_resid={m: float(res[m][0]["resid"].max()) for m in res},
                               speedup_vs_f64_plain=round(res["f64_plain"][1] / res[mode][1], 3),
                               f64_tiled_rel_err_vs_plain=float(np.max(np.abs(res["f64"][0]["evals"] - e64) /
-                                                                       np.abs(e64))))
+                                                                       np.abs(e64))),
+                              dgks_rel_err_vs_f64_plain=float(np.max(np.abs(res[mode + "_dgks"][0]["evals"] - e64) /
+                                                                     np.abs(e64))),
+                              reorth="classical Gram-Schmidt twice (the *_dgks run: second pass only when "
+                                     "the first shrinks w below 1/sqrt(2))")
     if not a.no_trlan:
         piv = torch.from_numpy(inputs.random_vector(h.dim, 1802)).to(dev)
         torch.cuda.synchronize()

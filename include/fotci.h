@@ -42,6 +42,12 @@ extern "C" {
 #define FOTCI_MODE_F64 1        /* float64 vectors; tiled kernels */
 #define FOTCI_MODE_F32 2        /* float32 vectors and matrix elements (pn on f32 MFMA) */
 
+/* Reorthogonalisation of each new Lanczos vector against all stored ones
+ * (classical Gram-Schmidt with float64 sums): */
+#define FOTCI_REORTH_CGS2 0     /* two passes, always */
+#define FOTCI_REORTH_DGKS 1     /* a second pass only when the first shrank the vector below
+                                   1/sqrt(2) of its norm (the Daniel-Gragg-Kaufman-Stewart test) */
+
 /* Jump kinds for fotci_jumps_count / fotci_jumps_export. */
 #define FOTCI_JUMP_PP2 0  /* proton two-body jumps */
 #define FOTCI_JUMP_NN2 1  /* neutron two-body jumps */
@@ -193,6 +199,7 @@ typedef struct {
     int32_t n_iter;   /* Lanczos iterations (Krylov dimension), n_keep <= n_iter */
     int32_t mode;     /* FOTCI_MODE_*: storage/arithmetic of vectors and apply_H */
     int32_t refine;   /* 1: float64 Rayleigh-quotient refinement of the Ritz vectors */
+    int32_t reorth;   /* FOTCI_REORTH_* */
 } fotci_lanczos_opts;
 
 /* Bytes of device workspace fotci_lanczos_lowest needs for these options. */
@@ -235,6 +242,7 @@ typedef struct {
     int32_t max_restarts;  /* restarts allowed (>= 0) */
     int32_t mode;          /* FOTCI_MODE_* */
     int32_t refine;        /* 1: float64 Rayleigh-quotient refinement of the Ritz vectors */
+    int32_t reorth;        /* FOTCI_REORTH_* */
     double tol;            /* convergence threshold (> 0) on the residual estimate */
 } fotci_trlan_opts;
 

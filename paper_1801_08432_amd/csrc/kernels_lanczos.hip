@@ -163,12 +163,20 @@ __device__ __forceinline__ void load_w(const double *__restrict__ w, int64_t r0,
 // basis vectors.
 template <typename T, bool FULL>
 __device__ __forceinline__ void multidot_body(const T *__restrict__ V, int64_t ld, int k, const double *__restrict__ w,
-                                              int64_t n, double *__restrict__ partial, double (*lds)[256]) {
+                                              int64_t n, double *__restrict__ partial, double *__restrict__ sq_partial,
+                                              double (*lds)[256]) {
     const int64_t r0 = (int64_t)blockIdx.x * kChunk;
     const int nb = gridDim.x;
     double wr[kRowsPerThread];
     load_w<T, FULL>(w, r0, n, wr);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (sq_partial) {   // ||w||^2 of the block's rows (before this pass)
+        double sq = 0.0;
+#pragma unroll
+        for (int e = 0; e < kRowsPerThread; ++e) sq += wr[e] * wr[e];
+        sq = block_sum(sq, &lds[0][0]);
+        if (threadIdx.x == 0) sq_partial[blockIdx.x] = sq;
+    }
     for (int j0 = 0; j0 < k; j0 += 256) {
         const int jn = min(256, k - j0);
         for (int jj = 0; jj < jn; jj += kJU) {
@@ -202,12 +210,12 @@ __device__ __forceinline__ void multidot_body(const T *__restrict__ V, int64_t l
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_multidot(const T *__restrict__ V, int64_t ld, int k,
                                                        const double *__restrict__ w, int64_t n,
-                                                       double *__restrict__ partial) {
+                                                       double *__restrict__ partial, double *__restrict__ sq_partial) {
     __shared__ double lds[kWaves][256];
     if ((int64_t)(blockIdx.x + 1) * kChunk <= n)
-        multidot_body<T, true>(V, ld, k, w, n, partial, lds);
+        multidot_body<T, true>(V, ld, k, w, n, partial, sq_partial, lds);
     else
-        multidot_body<T, false>(V, ld, k, w, n, partial, lds);
+        multidot_body<T, false>(V, ld, k, w, n, partial, sq_partial, lds);
 }
 
 // c[j] = sum_b partial[j*nb + b]; one block per j.
@@ -341,7 +349,7 @@ int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 // and small arrays.
 struct Layout {
     int64_t ld;   // basis leading dimension (elements): dim rounded up to 64
-    int64_t basis, scratch, y, w, partial, scal, coef, S, ritz, hy, total;
+    int64_t basis, scratch, y, w, partial, sq, scal, coef, S, ritz, hy, total;
 };
 
 Layout make_layout(int64_t dim, int es, int nvec, int nscr, int ncoef, int s_cols, int n_keep) {
@@ -359,6 +367,8 @@ Layout make_layout(int64_t dim, int es, int nvec, int nscr, int ncoef, int s_col
     const int64_t nb = std::max<int64_t>(chunk_blocks(dim), 2048);
     L.partial = off;
     off = a256(off + (int64_t)std::max(ncoef, 1) * nb * 8);
+    L.sq = off;
+    off = a256(off + nb * 8);
     L.scal = off;
     off = a256(off + 64 * 8);
     L.coef = off;
@@ -393,16 +403,21 @@ struct Lz {
     int64_t dim, ld;
     int sb, cb, mode, hi_mode;
     T *basis, *scratch, *y;
-    double *w, *partial, *scal, *coef, *Sd, *ritz, *hy;   // scal: [0] alpha [1] beta [2] norm [3] theta [4] resid
+    double *w, *partial, *sq, *scal, *coef, *Sd, *ritz, *hy;   // scal: [0] alpha [1] beta [2] norm [3] theta
+                                                              // [4] resid [5] norm before reorthogonalisation
+    int reorth;
+    int second_passes = 0;
 
-    Lz(const fotci_ham *h_, const Layout &L, int mode_, char *work, double *evecs, hipStream_t st_)
+    Lz(const fotci_ham *h_, const Layout &L, int mode_, int reorth_, char *work, double *evecs, hipStream_t st_)
         : h(h_), st(st_), dim(h_->j->b->dim), ld(L.ld), sb(stream_blocks(dim)), cb(chunk_blocks(dim)),
-          mode(mode_), hi_mode(mode_ == FOTCI_MODE_F64_PLAIN ? FOTCI_MODE_F64_PLAIN : FOTCI_MODE_F64) {
+          mode(mode_), hi_mode(mode_ == FOTCI_MODE_F64_PLAIN ? FOTCI_MODE_F64_PLAIN : FOTCI_MODE_F64),
+          reorth(reorth_) {
         basis = (T *)(work + L.basis);
         scratch = (T *)(work + L.scratch);
         y = (T *)(work + L.y);
         w = (double *)(work + L.w);
         partial = (double *)(work + L.partial);
+        sq = (double *)(work + L.sq);
         scal = (double *)(work + L.scal);
         coef = (double *)(work + L.coef);
         Sd = (double *)(work + L.S);
@@ -443,16 +458,30 @@ struct Lz {
             hipLaunchKernelGGL(k_subtract<T>, dim3(cb), dim3(kThreads), (size_t)(na + kWaves) * 8, st,
                                (const T *)basis, ld, na, (const double *)coef, w, dim, (double *)nullptr);
         }
-        for (int pass = 0; pass < 2; ++pass) {
+        // pass 1 (with DGKS also ||w|| before it); the subtract leaves ||w||^2 block sums in partial
+        auto pass = [&](bool norm_before) {
             hipLaunchKernelGGL(k_multidot<T>, dim3(cb), dim3(kThreads), 0, st, (const T *)basis, ld, i + 1,
-                               (const double *)w, dim, partial);
+                               (const double *)w, dim, partial, norm_before ? sq : (double *)nullptr);
             hipLaunchKernelGGL(k_reduce_rows, dim3(i + 1), dim3(kThreads), 0, st, (const double *)partial, cb, coef);
-            // the second pass also leaves the block sums of ||w||^2 in partial
             hipLaunchKernelGGL(k_subtract<T>, dim3(cb), dim3(kThreads), (size_t)(i + 1 + kWaves) * 8, st,
-                               (const T *)basis, ld, i + 1, (const double *)coef, w, dim,
-                               pass == 1 ? partial : (double *)nullptr);
+                               (const T *)basis, ld, i + 1, (const double *)coef, w, dim, partial);
+            hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, cb, scal + 1, 1);
+        };
+        const bool dgks = reorth == FOTCI_REORTH_DGKS;
+        pass(dgks);
+        bool second = true;
+        if (dgks) {
+            hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)sq, cb, scal + 5, 1);
+            double nn[2];
+            hip_check(hipMemcpyAsync(nn, scal + 1, 8, hipMemcpyDeviceToHost, st), "lanczos copy");
+            hip_check(hipMemcpyAsync(nn + 1, scal + 5, 8, hipMemcpyDeviceToHost, st), "lanczos copy");
+            hip_check(hipStreamSynchronize(st), "lanczos sync");
+            second = nn[0] < 0.7071067811865476 * nn[1];
         }
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, st, (const double *)partial, cb, scal + 1, 1);
+        if (second) {
+            pass(false);
+            ++second_passes;
+        }
         hip_check(hipGetLastError(), "lanczos launch");
         double ab[2];
         hip_check(hipMemcpyAsync(ab, scal, 16, hipMemcpyDeviceToHost, st), "lanczos copy");
@@ -517,7 +546,7 @@ struct Lz {
 template <typename T>
 void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, char *work, double *evals,
          double *resid, double *evecs, double *alpha_out, double *beta_out, hipStream_t st) {
-    Lz<T> z(h, standard_layout(h, o), o->mode, work, evecs, st);
+    Lz<T> z(h, standard_layout(h, o), o->mode, o->reorth, work, evecs, st);
     z.start(pivot);
     std::vector<double> al, be;
     const std::vector<double> none;
@@ -557,7 +586,7 @@ template <typename T>
 void run_trlan(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, char *work, double *evals,
                double *resid, double *evecs, int32_t *stats, hipStream_t st) {
     const Layout L = trlan_layout(h, o);
-    Lz<T> z(h, L, o->mode, work, evecs, st);
+    Lz<T> z(h, L, o->mode, o->reorth, work, evecs, st);
     const int kb = o->n_basis, nt = o->n_thick;
     z.start(pivot);
     std::vector<double> Tm((size_t)(kb + 1) * (kb + 1), 0.0);
@@ -634,6 +663,7 @@ void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *
                  double *evals, double *resid, double *evecs, double *alpha, double *beta, void *stream) {
     if (o->n_keep < 1 || o->n_keep > 16) fail(FOTCI_EINVAL, "n_keep must be in 1..16");
     if (o->n_iter < o->n_keep || o->n_iter > kMaxIter) fail(FOTCI_EINVAL, "n_iter must be in n_keep..4096");
+    if (o->reorth != FOTCI_REORTH_CGS2 && o->reorth != FOTCI_REORTH_DGKS) fail(FOTCI_EINVAL, "unknown reorth");
     if (work_bytes < lanczos_bytes(h, o)) fail(FOTCI_ENOMEM, "Lanczos workspace too small");
     if (((uintptr_t)work & 255u) != 0) fail(FOTCI_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
@@ -657,6 +687,7 @@ void check_trlan_opts(const fotci_trlan_opts *o) {
         fail(FOTCI_EINVAL, "n_basis must be in n_thick+2..4095");
     if (o->max_restarts < 0) fail(FOTCI_EINVAL, "max_restarts must be >= 0");
     if (!(o->tol > 0.0)) fail(FOTCI_EINVAL, "tol must be positive");
+    if (o->reorth != FOTCI_REORTH_CGS2 && o->reorth != FOTCI_REORTH_DGKS) fail(FOTCI_EINVAL, "unknown reorth");
     if (o->mode != FOTCI_MODE_F64 && o->mode != FOTCI_MODE_F64_PLAIN && o->mode != FOTCI_MODE_F32)
         fail(FOTCI_EINVAL, "unknown mode");
 }

@@ -19,6 +19,7 @@ MODE_F64_PLAIN = 0
 MODE_F64 = 1
 MODE_F32 = 2
 MODES = {"f64_plain": MODE_F64_PLAIN, "f64": MODE_F64, "f32": MODE_F32}
+REORTH = {"cgs2": 0, "dgks": 1}
 
 JUMP_PP2, JUMP_NN2, JUMP_P1, JUMP_N1 = 0, 1, 2, 3
 
@@ -43,13 +44,13 @@ class FotciError(RuntimeError):
 
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("n_keep", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("refine", ctypes.c_int32)]
+                ("refine", ctypes.c_int32), ("reorth", ctypes.c_int32)]
 
 
 class TrlanOpts(ctypes.Structure):
     _fields_ = [("n_keep", ctypes.c_int32), ("n_thick", ctypes.c_int32), ("n_basis", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("mode", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("tol", ctypes.c_double)]
+                ("reorth", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 _lib = None
@@ -288,18 +289,18 @@ class Hamiltonian:
         return rp, rn
 
     def lanczos_workspace_bytes(self, n_keep, n_iter, mode="f64", refine=True):
-        o = LanczosOpts(n_keep, n_iter, MODES[mode] if isinstance(mode, str) else int(mode), int(refine))
+        o = LanczosOpts(n_keep, n_iter, MODES[mode] if isinstance(mode, str) else int(mode), int(refine), 0)
         n = lib().fotci_lanczos_workspace_bytes(self._h, ctypes.byref(o))
         if n < 0:
             _check(int(n))
         return int(n)
 
     def lanczos_lowest(self, pivot, n_keep, n_iter, mode="f64", refine=True, want_vectors=False,
-                       work=None, stream=None):
+                       work=None, stream=None, reorth="cgs2"):
         """Lowest n_keep eigenvalues; returns dict(evals, resid, alpha, beta[, evecs])."""
         import torch
         m = MODES[mode] if isinstance(mode, str) else int(mode)
-        o = LanczosOpts(n_keep, n_iter, m, int(refine))
+        o = LanczosOpts(n_keep, n_iter, m, int(refine), REORTH[reorth])
         nbytes = self.lanczos_workspace_bytes(n_keep, n_iter, m, refine)
         if work is None or work.numel() < nbytes + 256:
             work = torch.empty(nbytes + 256, dtype=torch.uint8, device=pivot.device)
@@ -321,11 +322,11 @@ class Hamiltonian:
         return out
 
     def lanczos_thick_restart(self, pivot, n_keep, n_thick, n_basis, max_restarts=50, mode="f64", refine=True,
-                              tol=1e-10, want_vectors=False, stream=None):
+                              tol=1e-10, want_vectors=False, stream=None, reorth="cgs2"):
         """Thick-restart Lanczos; returns dict(evals, resid, restarts, applies, converged[, evecs])."""
         import torch
         m = MODES[mode] if isinstance(mode, str) else int(mode)
-        o = TrlanOpts(n_keep, n_thick, n_basis, max_restarts, m, int(refine), float(tol))
+        o = TrlanOpts(n_keep, n_thick, n_basis, max_restarts, m, int(refine), REORTH[reorth], float(tol))
         nbytes = lib().fotci_trlan_workspace_bytes(self._h, ctypes.byref(o))
         if nbytes < 0:
             _check(int(nbytes))
@@ -348,7 +349,7 @@ class Hamiltonian:
 
     def trlan_workspace_bytes(self, n_keep, n_thick, n_basis, mode="f64", max_restarts=50, tol=1e-10):
         m = MODES[mode] if isinstance(mode, str) else int(mode)
-        o = TrlanOpts(n_keep, n_thick, n_basis, max_restarts, m, 1, float(tol))
+        o = TrlanOpts(n_keep, n_thick, n_basis, max_restarts, m, 1, 0, float(tol))
         n = lib().fotci_trlan_workspace_bytes(self._h, ctypes.byref(o))
         if n < 0:
             _check(int(n))

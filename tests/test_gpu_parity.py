@@ -181,6 +181,27 @@ def test_lanczos_f32_vs_f64_pf_4p4n():
     assert np.all(rel <= 1e-5)
 
 
+def test_lanczos_dgks_reorthogonalisation():
+    """The conditional second Gram-Schmidt pass: float64 against ARPACK on
+    sd_6p6n, float32 vectors against the always-twice float64 run on pf_4p4n."""
+    import scipy.sparse.linalg as sla
+    w, h, o, prep = setup("sd_6p6n")
+    op = of.Operator(prep, w)
+    lo = sla.LinearOperator(op.shape, matvec=op.matvec, dtype=np.float64)
+    ref = np.sort(sla.eigsh(lo, k=10, which="SA", tol=1e-13, ncv=60,
+                            v0=inputs.random_vector(h.dim, 17))[0])
+    piv = torch.from_numpy(inputs.random_vector(h.dim, 18)).to(DEV)
+    r = h.lanczos_lowest(piv, 10, 300, mode="f64", reorth="dgks")
+    assert np.allclose(r["evals"], ref, rtol=1e-9, atol=0)
+    w, h, o, prep = setup("pf_4p4n")
+    piv = torch.from_numpy(inputs.random_vector(h.dim, 19)).to(DEV)
+    r64 = h.lanczos_lowest(piv, 10, 300, mode="f64")
+    r32 = h.lanczos_lowest(piv, 10, 300, mode="f32", reorth="dgks")
+    rel = np.abs(r32["evals"] - r64["evals"]) / np.abs(r64["evals"])
+    _say("[lanczos f32 dgks vs f64] rel err", rel)
+    assert np.all(rel <= 1e-5)
+
+
 def test_vjp_matches_oracle_densities():
     for name in ("sd_2p2n", "sd_6p6n"):
         w, h, o, prep = setup(name)
