@@ -556,3 +556,89 @@ def test_one_body_density_c_matches_python():
     rp, rn = oh.one_body_densities(b, g, x)
     cp, cn = of.one_body_densities(of.Prepared(b), g, x)
     assert np.max(np.abs(rp - cp)) < 1e-12 and np.max(np.abs(rn - cn)) < 1e-12
+
+
+# ----------------------------------- J-coupled elements and their decoupling
+from oracle import angmom as am  # noqa: E402
+
+
+def test_clebsch_gordan_values_and_symmetries():
+    s = 1 / math.sqrt(2)
+    assert abs(am.clebsch_gordan(1, 1, 1, -1, 2, 0) - s) < 1e-15
+    assert abs(am.clebsch_gordan(1, 1, 1, -1, 0, 0) - s) < 1e-15
+    assert abs(am.clebsch_gordan(1, -1, 1, 1, 0, 0) + s) < 1e-15
+    assert abs(am.clebsch_gordan(2, 2, 2, -2, 0, 0) - 1 / math.sqrt(3)) < 1e-15
+    assert abs(am.clebsch_gordan(2, 2, 2, 0, 4, 2) - s) < 1e-15        # (1 1, 1 0 | 2 1)
+    assert abs(am.clebsch_gordan(3, 1, 1, 1, 2, 2) + math.sqrt(0.25)) < 1e-15   # (3/2 1/2, 1/2 1/2 | 1 1) = -1/2
+    for tj in (1, 3, 5, 7):   # (j m, j -m | 0 0) = (-1)^(j-m) / sqrt(2j+1)
+        for tm in range(-tj, tj + 1, 2):
+            ref = (-1) ** ((tj - tm) // 2) / math.sqrt(tj + 1)
+            assert abs(am.clebsch_gordan(tj, tm, tj, -tm, 0, 0) - ref) < 1e-14
+    for tj1, tj2 in ((1, 3), (5, 7), (3, 3), (7, 7)):
+        for tJ in range(abs(tj1 - tj2), tj1 + tj2 + 1, 2):
+            for tm1 in range(-tj1, tj1 + 1, 2):
+                for tm2 in range(-tj2, tj2 + 1, 2):
+                    a = am.clebsch_gordan(tj1, tm1, tj2, tm2, tJ, tm1 + tm2)
+                    b = am.clebsch_gordan(tj2, tm2, tj1, tm1, tJ, tm1 + tm2)
+                    assert abs(b - (-1) ** ((tj1 + tj2 - tJ) // 2) * a) < 1e-14
+        # orthonormality of the coupled basis
+        for tM in range(-(tj1 + tj2), tj1 + tj2 + 1, 2):
+            Js = [tJ for tJ in range(abs(tj1 - tj2), tj1 + tj2 + 1, 2) if abs(tM) <= tJ]
+            rows = [(m1, tM - m1) for m1 in range(-tj1, tj1 + 1, 2) if abs(tM - m1) <= tj2]
+            C = np.array([[am.clebsch_gordan(tj1, m1, tj2, m2, tJ, tM) for (m1, m2) in rows] for tJ in Js])
+            assert np.max(np.abs(C @ C.T - np.eye(len(Js)))) < 1e-13
+
+
+def test_pair_states_are_normalised_and_pauli():
+    ms = ob.m_states((3, 5))
+    for a, b in ((0, 0), (0, 1), (1, 1)):
+        ja, jb = (3, 5)[a], (3, 5)[b]
+        for tJ in range(abs(ja - jb), ja + jb + 1, 2):
+            st = am.pair_state(ms, a, b, tJ, 0)
+            norm = sum(v * v for v in st.values())
+            if a == b and (tJ // 2) % 2 == 1:
+                assert norm < 1e-28          # two identical nucleons in one orbit: odd J vanish
+            else:
+                assert abs(norm - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("space", [(1, 3), (1, 3, 5)])
+def test_decoupled_j_squared_matches_direct_construction(space):
+    """J^2 written as J-coupled elements and decoupled with Clebsch-Gordan
+    coefficients equals J^2 built from the j_z, j_+- matrices."""
+    direct = am.j_squared_direct(space)
+    eps, pp, nn, pn = am.j_squared_coupled(space)
+    dec = am.decouple(space, pp, nn, pn)
+    assert np.allclose(eps, direct["eps_p"], atol=1e-14)
+    for k in ("v_pp", "v_nn", "v_pn"):
+        assert np.max(np.abs(dec[k] - direct[k])) < 1e-12, k
+
+
+def test_decoupled_two_particle_spectrum():
+    """Two protons, no single-particle energies: the M-block spectrum is the
+    union over J >= |M| of the eigenvalues of each J-coupled V_J matrix."""
+    space = (1, 3, 5)
+    rng = np.random.default_rng(12)
+    pairs_j = {}
+    for a in range(3):
+        for b in range(a, 3):
+            for tJ in range(abs(space[a] - space[b]), space[a] + space[b] + 1, 2):
+                if a == b and (tJ // 2) % 2:
+                    continue
+                pairs_j.setdefault(tJ, []).append((a, b))
+    elems, blocks = [], {}
+    for tJ, pl in pairs_j.items():
+        n = len(pl)
+        m = rng.standard_normal((n, n))
+        m = m + m.T
+        blocks[tJ] = np.linalg.eigvalsh(m)
+        for i in range(n):
+            for k in range(i, n):
+                elems.append(pl[i] + pl[k] + (tJ, m[i, k]))
+    dec = am.decouple(space, pp=elems)
+    inter = dict(eps_p=np.zeros(3), eps_n=np.zeros(3), v_pp=dec["v_pp"], v_nn=dec["v_nn"], v_pn=dec["v_pn"])
+    for two_M in (0, 2, 4):
+        b = ob.build_basis(space, 2, 0, two_M)
+        ev = np.linalg.eigvalsh(oh.dense_h(b, inter))
+        ref = np.sort(np.concatenate([blocks[tJ] for tJ in blocks if tJ >= two_M]))
+        assert np.allclose(ev, ref, atol=1e-12), two_M
