@@ -88,6 +88,40 @@ def cpu_baseline(w, x, seconds):
                        (r0, r0 + rows, o.dim, 100.0 * rows / o.dim, t))
 
 
+def jcoupled_leg(w, mode, n_iter):
+    """Rotational invariance at full size: a random J-coupled interaction on
+    the same space and particle numbers, decoupled by the library; lowest 5
+    by Lanczos in the bench mode, then <J^2> of each Ritz vector with J^2
+    itself decoupled from J-coupled form and applied in float64."""
+    import torch
+    from paper_1801_08432_amd import fotci, inputs
+    from oracle import angmom as am   # J^2 as J-coupled elements (a list of numbers, no arithmetic of H)
+    dev = "cuda:0"
+    space = w["two_j"]
+    ep, en, pp, nn, pn = inputs.random_jcoupled(space, 1805)
+    t0 = time.perf_counter()
+    dec = fotci.decouple_tbme(space, pp, nn, pn)
+    t_dec = time.perf_counter() - t0
+    h = fotci.Hamiltonian.build(space, w["Z"], w["N"], w["two_M"], dict(eps_p=ep, eps_n=en, **dec), device=dev)
+    eps, jp, jn, jpn = am.j_squared_coupled(space)
+    hj = fotci.Hamiltonian.build(space, w["Z"], w["N"], w["two_M"],
+                                 dict(eps_p=eps, eps_n=eps.copy(), **fotci.decouple_tbme(space, jp, jn, jpn)),
+                                 device=dev)
+    piv = torch.from_numpy(inputs.random_vector(h.dim, 1806)).to(dev)
+    r = h.lanczos_lowest(piv, 5, n_iter, mode=mode, want_vectors=True)
+    js, dev_max = [], 0.0
+    for k in range(5):
+        v = r["evecs"][k].contiguous()
+        j2 = float(torch.dot(v, hj.apply(v, mode="f64")))
+        J = int(round((-1 + np.sqrt(1 + 4 * max(j2, 0.0))) / 2))
+        js.append(J)
+        dev_max = max(dev_max, abs(j2 - J * (J + 1)))
+    del h, hj
+    torch.cuda.empty_cache()
+    return dict(decouple_ms=round(1e3 * t_dec, 2), n_elements=len(pp) + len(nn) + len(pn), evals=r["evals"].tolist(),
+                J=js, max_abs_J2_deviation=dev_max, max_resid=float(r["resid"].max()))
+
+
 def density_leg(h, w, reps=5):
     """Time the one-body transition densities of two float64 vectors; the
     streamed bytes are the g and x rows (proton side) and columns (neutron
@@ -134,6 +168,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--no-trlan", action="store_true")
+    ap.add_argument("--no-jcoupled", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 1 GiB (float32) once, a known-size kernel for HBM counter calibration")
@@ -276,6 +311,8 @@ def main():
         log("[bench] thick restart: %s" % tr)
     if not a.no_density:
         out["one_body_density"] = density_leg(h, w)
+    if not a.no_jcoupled:
+        out["jcoupled"] = jcoupled_leg(w, mode, a.lanczos_iters)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, xs, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -148,6 +148,36 @@ int fotci_ham_set_values(fotci_ham *h, const double *spe_p, const double *spe_n,
 /* Bytes of device workspace fotci_ham_upload needs (>= 0), or a negative code. */
 int64_t fotci_ham_workspace_bytes(const fotci_ham *h);
 
+/* One J-coupled two-body matrix element V_J(ab, cd) in MeV: orbit indices
+ * (0-based, in the orbit order of the basis) and 2J. */
+typedef struct {
+    int32_t a, b, c, d;
+    int32_t two_J;
+    double v;
+} fotci_tbme;
+
+/*
+ * fotci_decouple_tbme -- the m-scheme arrays fotci_set_interaction takes,
+ * from J-coupled two-body matrix elements between normalised two-body states
+ * of good J (App. A, "The Hamiltonian and other operators in second
+ * quantization", eq. hamdef). For like particles (al < be, ga < de m-states
+ * of orbits a <= b, c <= d):
+ *   V[(al be),(ga de)] = sum_J zeta_ab zeta_cd V_J(ab,cd)
+ *                        (j_a m_al j_b m_be | J M) (j_c m_ga j_d m_de | J M),
+ * zeta_ab = sqrt(2) if a == b else 1; for a proton-neutron pair (a, c proton
+ * orbits, b, d neutron orbits) the same product-state sum without zeta.
+ * two_j[n_orbits], parity[n_orbits] (NULL: all +1) define the m-states as in
+ * fotci_build_basis. Each (ab, cd) is given once and (cd, ab) is implied;
+ * repeated elements add. Outputs (host, overwritten, exactly symmetric; each
+ * may be NULL): v_pp, v_nn [n_pairs^2], v_pn [N_s^4]. FOTCI_EINVAL for an
+ * orbit index out of range, a > b or c > d for like particles, 2J outside the
+ * coupling range of a pair, a parity change, a nonzero odd-J element of two
+ * like particles in one orbit, or a non-finite value. Host only.
+ */
+int fotci_decouple_tbme(int32_t n_orbits, const int32_t *two_j, const int32_t *parity, int32_t n_pp,
+                        const fotci_tbme *pp, int32_t n_nn, const fotci_tbme *nn, int32_t n_pn,
+                        const fotci_tbme *pn, double *v_pp, double *v_nn, double *v_pn);
+
 /*
  * fotci_ham_upload -- copy the jump tables and interaction into the
  * caller-owned device workspace (256-byte aligned, `bytes` >= the size from

@@ -56,6 +56,8 @@ extern "C" int fotci_ham_set_values_impl(fotci_ham *, const double *, const doub
                                          const double *, void *);
 extern "C" int fotci_ham_op_counts_impl(const fotci_ham *, int64_t *, int64_t *, int64_t *, int64_t *);
 extern "C" int fotci_ham_pn_work_impl(const fotci_ham *, int64_t *, int64_t *, int64_t *);
+extern "C" int fotci_decouple_tbme_impl(int32_t, const int32_t *, const int32_t *, int32_t, const fotci_tbme *, int32_t,
+                                        const fotci_tbme *, int32_t, const fotci_tbme *, double *, double *, double *);
 extern "C" int fotci_ham_set_pn_private_rows_impl(fotci_ham *, int32_t);
 
 extern "C" {
@@ -243,6 +245,13 @@ int fotci_lanczos_thick_restart(const fotci_ham *h, const fotci_trlan_opts *o, c
 
 int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn, int64_t *ops_diag) {
     return guard([&] { return fotci_ham_op_counts_impl(h, ops_pp, ops_nn, ops_pn, ops_diag); });
+}
+
+int fotci_decouple_tbme(int32_t n_orbits, const int32_t *two_j, const int32_t *parity, int32_t n_pp,
+                        const fotci_tbme *pp, int32_t n_nn, const fotci_tbme *nn, int32_t n_pn, const fotci_tbme *pn,
+                        double *v_pp, double *v_nn, double *v_pn) {
+    return guard(
+        [&] { return fotci_decouple_tbme_impl(n_orbits, two_j, parity, n_pp, pp, n_nn, nn, n_pn, pn, v_pp, v_nn, v_pn); });
 }
 
 int fotci_ham_pn_work(const fotci_ham *h, int64_t *tile_visits, int64_t *mfma_instr, int64_t *gather_slots) {

@@ -31,7 +31,7 @@ EXPORTED = [
     "fotci_lanczos_workspace_bytes",
     "fotci_lanczos_lowest", "fotci_trlan_workspace_bytes", "fotci_lanczos_thick_restart",
     "fotci_ham_op_counts", "fotci_ham_pn_work", "fotci_ham_set_pn_private_rows",
-    "fotci_tridiag_eigh", "fotci_sym_eigh", "fotci_profile_start",
+    "fotci_tridiag_eigh", "fotci_sym_eigh", "fotci_decouple_tbme", "fotci_profile_start",
     "fotci_profile_stop",
 ]
 
@@ -45,6 +45,11 @@ class FotciError(RuntimeError):
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("n_keep", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("refine", ctypes.c_int32), ("reorth", ctypes.c_int32)]
+
+
+class Tbme(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_int32), ("b", ctypes.c_int32), ("c", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("two_J", ctypes.c_int32), ("v", ctypes.c_double)]
 
 
 class TrlanOpts(ctypes.Structure):
@@ -93,6 +98,7 @@ def lib():
         "fotci_ham_set_pn_private_rows": (ctypes.c_int, [P, ctypes.c_int32]),
         "fotci_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
         "fotci_sym_eigh": (ctypes.c_int, [I32, P, P, P]),
+        "fotci_decouple_tbme": (ctypes.c_int, [I32, P, P, I32, P, I32, P, I32, P, P, P, P]),
         "fotci_profile_start": (ctypes.c_int, [P, I32]),
         "fotci_profile_stop": (ctypes.c_int, [P, P, P, P, P]),
     }
@@ -371,6 +377,30 @@ class Hamiltonian:
         if getattr(self, "_h", None) is not None and _lib is not None:
             _lib.fotci_free_ham(self._h)
             self._h = None
+
+
+def decouple_tbme(two_j, pp=(), nn=(), pn=(), parity=None):
+    """m-scheme (v_pp, v_nn, v_pn) from J-coupled elements (a, b, c, d, two_J, V) (host)."""
+    tj = np.ascontiguousarray(two_j, dtype=np.int32)
+    par = None if parity is None else np.ascontiguousarray(parity, dtype=np.int32)
+    ns = int(np.sum(tj + 1))
+    npairs = ns * (ns - 1) // 2
+
+    def arr(elems):
+        elems = list(elems)
+        a = (Tbme * max(len(elems), 1))()
+        for i, (x, y, z, w, tJ, v) in enumerate(elems):
+            a[i] = Tbme(int(x), int(y), int(z), int(w), int(tJ), float(v))
+        return len(elems), a
+
+    n_pp, app = arr(pp)
+    n_nn, ann = arr(nn)
+    n_pn, apn = arr(pn)
+    out = dict(v_pp=np.zeros((npairs, npairs)), v_nn=np.zeros((npairs, npairs)), v_pn=np.zeros((ns * ns, ns * ns)))
+    _check(lib().fotci_decouple_tbme(len(tj), _np_ptr(tj), _np_ptr(par) if par is not None else None, n_pp, app,
+                                     n_nn, ann, n_pn, apn, _np_ptr(out["v_pp"]), _np_ptr(out["v_nn"]),
+                                     _np_ptr(out["v_pn"])))
+    return out
 
 
 def sym_eigh(a):

@@ -124,3 +124,46 @@ def workload(name):
 def random_vector(n, seed, dtype=np.float64):
     """Seeded N(0,1) vector of length n."""
     return np.random.default_rng(seed).standard_normal(n).astype(dtype)
+
+
+def random_jcoupled(two_j, seed, parity=None, scale=1.0):
+    """Seeded random rotationally invariant interaction as J-coupled elements.
+
+    For every 2J, one symmetric N(0,1) matrix over the allowed orbit pairs of
+    each kind (like particles: a <= b, even J when a == b; proton-neutron: all
+    (a, b)), parity-conserving pairs only; single-particle energies U(-5,5)
+    per orbit. Draw order from ``numpy.random.default_rng(seed)``: eps_p,
+    eps_n, then pp, nn, pn, each by ascending 2J, upper triangle row-major.
+    Returns (eps_p, eps_n, pp, nn, pn), the element lists as
+    (a, b, c, d, two_J, V) tuples with (ab) <= (cd) in list order.
+    """
+    rng = np.random.default_rng(seed)
+    n = len(two_j)
+    par = [1] * n if parity is None else list(parity)
+    eps_p = rng.uniform(-5.0, 5.0, n)
+    eps_n = rng.uniform(-5.0, 5.0, n)
+    max_tJ = 2 * max(two_j)
+
+    def draw(like):
+        out = []
+        for tJ in range(0, max_tJ + 1, 2):
+            pl = []
+            for a in range(n):
+                for b in range(a if like else 0, n):
+                    if not (abs(two_j[a] - two_j[b]) <= tJ <= two_j[a] + two_j[b]):
+                        continue
+                    if like and a == b and (tJ // 2) % 2:
+                        continue
+                    pl.append((a, b))
+            for i in range(len(pl)):
+                for k in range(i, len(pl)):
+                    (a, b), (c, d) = pl[i], pl[k]
+                    if par[a] * par[b] != par[c] * par[d]:
+                        continue
+                    out.append((a, b, c, d, tJ, float(rng.standard_normal()) * scale))
+        return out
+
+    pp = draw(True)
+    nn = draw(True)
+    pn = draw(False)
+    return eps_p, eps_n, pp, nn, pn

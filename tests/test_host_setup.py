@@ -256,3 +256,42 @@ def test_thick_restart_options_are_checked():
                 dict(n_keep=0, n_thick=10, n_basis=20), dict(n_keep=5, n_thick=10, n_basis=20, tol=0.0)]:
         with pytest.raises(fotci.FotciError):
             h.trlan_workspace_bytes(**bad)
+
+
+@pytest.mark.parametrize("space,parity", [((1, 3, 5), None), ((1, 3, 5, 7), None), ((1, 3, 3), (1, -1, 1))])
+def test_decoupling_matches_oracle(space, parity):
+    from oracle import angmom as am
+    ep, en, pp, nn, pn = inputs.random_jcoupled(space, 9, parity)
+    lib = fotci.decouple_tbme(space, pp, nn, pn, parity)
+    ora = am.decouple(space, pp, nn, pn, parity)
+    for k in ("v_pp", "v_nn", "v_pn"):
+        assert np.max(np.abs(lib[k] - ora[k])) < 1e-13, k
+        assert np.array_equal(lib[k], lib[k].T), k
+    # the arrays pass the Hamiltonian's checks (exact symmetry, Jz and parity zeros)
+    inter = dict(eps_p=ep, eps_n=en, **lib)
+    b = fotci.Basis(space, 2, 2, 0, 1, orbit_parity=parity)
+    fotci.Hamiltonian(fotci.Jumps(b), inter)
+
+
+def test_decoupled_j_squared_from_library():
+    from oracle import angmom as am
+    space = (1, 3, 5)
+    eps, pp, nn, pn = am.j_squared_coupled(space)
+    lib = fotci.decouple_tbme(space, pp, nn, pn)
+    direct = am.j_squared_direct(space)
+    for k in ("v_pp", "v_nn", "v_pn"):
+        assert np.max(np.abs(lib[k] - direct[k])) < 1e-12, k
+
+
+@pytest.mark.parametrize("elem,kind", [((1, 0, 1, 0, 2, 1.0), "pp"), ((0, 1, 0, 1, 8, 1.0), "pp"),
+                                       ((2, 2, 2, 2, 2, 1.0), "nn"), ((0, 5, 0, 1, 2, 1.0), "pn"),
+                                       ((0, 1, 0, 1, 3, 1.0), "pn")])
+def test_decoupling_rejects_bad_elements(elem, kind):
+    with pytest.raises(fotci.FotciError) as e:
+        fotci.decouple_tbme((1, 3, 5), **{kind: [elem]})
+    assert e.value.code == -1
+
+
+def test_decoupling_rejects_parity_change():
+    with pytest.raises(fotci.FotciError):
+        fotci.decouple_tbme((1, 3), pn=[(0, 0, 0, 1, 2, 1.0)], parity=(1, -1))
