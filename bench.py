@@ -94,8 +94,7 @@ def jcoupled_leg(w, mode, n_iter):
     by Lanczos in the bench mode, then <J^2> of each Ritz vector with J^2
     itself decoupled from J-coupled form and applied in float64."""
     import torch
-    from paper_1801_08432_amd import fotci, inputs
-    from oracle import angmom as am   # J^2 as J-coupled elements (a list of numbers, no arithmetic of H)
+    from paper_1801_08432_amd import fotci, inputs, observables
     dev = "cuda:0"
     space = w["two_j"]
     ep, en, pp, nn, pn = inputs.random_jcoupled(space, 1805)
@@ -103,7 +102,7 @@ def jcoupled_leg(w, mode, n_iter):
     dec = fotci.decouple_tbme(space, pp, nn, pn)
     t_dec = time.perf_counter() - t0
     h = fotci.Hamiltonian.build(space, w["Z"], w["N"], w["two_M"], dict(eps_p=ep, eps_n=en, **dec), device=dev)
-    eps, jp, jn, jpn = am.j_squared_coupled(space)
+    eps, jp, jn, jpn = observables.j_squared(space)
     hj = fotci.Hamiltonian.build(space, w["Z"], w["N"], w["two_M"],
                                  dict(eps_p=eps, eps_n=eps.copy(), **fotci.decouple_tbme(space, jp, jn, jpn)),
                                  device=dev)

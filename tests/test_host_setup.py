@@ -295,3 +295,16 @@ def test_decoupling_rejects_bad_elements(elem, kind):
 def test_decoupling_rejects_parity_change():
     with pytest.raises(fotci.FotciError):
         fotci.decouple_tbme((1, 3), pn=[(0, 0, 0, 1, 2, 1.0)], parity=(1, -1))
+
+
+def test_package_j_squared_elements_match_oracle():
+    """The package's J^2 element list decouples to the oracle's directly built J^2."""
+    from oracle import angmom as am
+    from paper_1801_08432_amd import observables
+    for space in ((1, 3, 5), (1, 3, 5, 7)):
+        eps, pp, nn, pn = observables.j_squared(space)
+        lib = fotci.decouple_tbme(space, pp, nn, pn)
+        direct = am.j_squared_direct(space)
+        assert np.allclose(eps, direct["eps_p"], atol=0)
+        for k in ("v_pp", "v_nn", "v_pn"):
+            assert np.max(np.abs(lib[k] - direct[k])) < 1e-12, k
