@@ -88,11 +88,12 @@ def cpu_baseline(w, x, seconds):
                        (r0, r0 + rows, o.dim, 100.0 * rows / o.dim, t))
 
 
-def jcoupled_leg(w, mode, n_iter):
+def jcoupled_leg(w, mode):
     """Rotational invariance at full size: a random J-coupled interaction on
     the same space and particle numbers, decoupled by the library; lowest 5
-    by Lanczos in the bench mode, then <J^2> of each Ritz vector with J^2
-    itself decoupled from J-coupled form and applied in float64."""
+    converged by thick-restart Lanczos in the bench mode, then <J^2> of each
+    Ritz vector with J^2 itself decoupled from J-coupled form and applied in
+    float64."""
     import torch
     from paper_1801_08432_amd import fotci, inputs, observables
     dev = "cuda:0"
@@ -107,7 +108,9 @@ def jcoupled_leg(w, mode, n_iter):
                                  dict(eps_p=eps, eps_n=eps.copy(), **fotci.decouple_tbme(space, jp, jn, jpn)),
                                  device=dev)
     piv = torch.from_numpy(inputs.random_vector(h.dim, 1806)).to(dev)
-    r = h.lanczos_lowest(piv, 5, n_iter, mode=mode, want_vectors=True)
+    t0 = time.perf_counter()
+    r = h.lanczos_thick_restart(piv, 5, 20, 60, max_restarts=100, mode=mode, tol=1e-9, want_vectors=True)
+    t_tr = time.perf_counter() - t0
     js, dev_max = [], 0.0
     for k in range(5):
         v = r["evecs"][k].contiguous()
@@ -118,7 +121,9 @@ def jcoupled_leg(w, mode, n_iter):
     del h, hj
     torch.cuda.empty_cache()
     return dict(decouple_ms=round(1e3 * t_dec, 2), n_elements=len(pp) + len(nn) + len(pn), evals=r["evals"].tolist(),
-                J=js, max_abs_J2_deviation=dev_max, max_resid=float(r["resid"].max()))
+                J=js, max_abs_J2_deviation=dev_max, max_resid=float(r["resid"].max()),
+                thick_restart=dict(seconds=round(t_tr, 2), restarts=r["restarts"], applies=r["applies"],
+                                   converged=r["converged"]))
 
 
 def density_leg(h, w, reps=5):
@@ -311,7 +316,7 @@ def main():
     if not a.no_density:
         out["one_body_density"] = density_leg(h, w)
     if not a.no_jcoupled:
-        out["jcoupled"] = jcoupled_leg(w, mode, a.lanczos_iters)
+        out["jcoupled"] = jcoupled_leg(w, mode)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, xs, a.cpu_seconds)
     print(json.dumps(out), flush=True)
