@@ -41,7 +41,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;      // threads per workgroup (4 waves)
 constexpr int kTile = 8;     // rows (nn kernel) / columns (pp kernel) per tile
-constexpr int kLdsTile = 65536;  // bytes of LDS for a staged tile
+constexpr int kLdsTile = 131072;  // bytes of LDS for a staged tile (gfx950: up to 160 KiB per workgroup)
 
 template <typename T>
 struct Mma;
