@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kT) void k_ell_values(const int32_t *__restrict__ e
 }
 
 // ------------------------------------------------------------ diagonal + nn
-// RT rows are staged per pass (RT * max_nn * sizeof(T) <= 64 KiB).
+// RT rows are staged per pass (RT * max_nn * sizeof(T) <= kLdsTile).
 template <typename T, int RT>
 __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
 }
 
 // ---------------------------------------------------------------------- pp
-// CT columns are staged per pass (max_np * CT * sizeof(T) <= 64 KiB).
+// CT columns are staged per pass (max_np * CT * sizeof(T) <= kLdsTile).
 template <typename T, int CT>
 __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
