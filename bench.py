@@ -179,7 +179,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on exactly one GPU: the path is built and measured on one "
-              "MI355X only (multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "MI355X only (multi-GPU sharding is described in the design notes and not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
