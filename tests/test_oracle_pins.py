@@ -481,6 +481,70 @@ def test_oracle_lanczos_full_krylov_recovers_spectrum():
         assert np.linalg.norm(r) < 1e-6
 
 
+# ------------------------------------- block Lanczos (Ch. "Block Lanczos")
+@pytest.mark.parametrize("nb", [2, 4, 8])
+def test_oracle_block_lanczos_full_krylov_recovers_spectrum(nb):
+    """dim / n_block block iterations span the whole space: T's eigenvalues are
+    H's (library eigensolver), and the basis is orthonormal with T = V^T H V."""
+    space = inputs.SD_SHELL_LIKE
+    inter, rng = inputs.random_interaction(space, 1801084321)
+    b = ob.build_basis(space, 2, 2, 0)
+    H = oh.dense_h(b, inter)
+    ev = np.linalg.eigvalsh(H)
+    got, T, k, V = ol.block_lanczos(lambda X: H @ X, rng.standard_normal((b.dim, nb)), b.dim // nb, b.dim)
+    assert k * nb == b.dim
+    assert np.allclose(got, ev, atol=1e-9 * np.max(np.abs(ev)))
+    assert np.allclose(V.T @ V, np.eye(b.dim), atol=1e-12)
+    assert np.allclose(V.T @ H @ V, T, atol=1e-10 * np.max(np.abs(ev)))
+
+
+def test_oracle_block_lanczos_projection_and_lowest_states():
+    """A partial run: the basis stays orthonormal, T is the projection of H on
+    it (this fixes where B_n and B_n^T go), and the lowest five Ritz values
+    converge to H's."""
+    space = inputs.SD_SHELL_LIKE
+    inter, rng = inputs.random_interaction(space, 7)
+    b = ob.build_basis(space, 2, 2, 0)
+    H = oh.dense_h(b, inter)
+    ev = np.linalg.eigvalsh(H)
+    got, T, k, V = ol.block_lanczos(lambda X: H @ X, rng.standard_normal((b.dim, 4)), 40, 5)
+    assert k == 40
+    assert np.allclose(V.T @ V, np.eye(160), atol=1e-12)
+    assert np.allclose(V.T @ H @ V, T, atol=1e-10 * np.max(np.abs(ev)))
+    assert np.allclose(got, ev[:5], rtol=1e-10)
+    # the one-vector block is standard Lanczos: the same Ritz values
+    v0 = rng.standard_normal(b.dim)
+    one, _, _, _ = ol.block_lanczos(lambda X: H @ X, v0[:, None], 100, 5)
+    std, _, _, _ = ol.lanczos(lambda v: H @ v, v0, 100, 5)
+    assert np.allclose(one, std, rtol=1e-12)
+
+
+@pytest.mark.parametrize("two_j,n,two_M,nb", [(9, 4, 0, 4), (7, 4, 0, 4), (9, 5, 1, 4), (9, 4, 0, 8)])
+def test_oracle_block_lanczos_resolves_degenerate_seniority_levels(two_j, n, two_M, nb):
+    """Single-j pairing: a block of n_block vectors finds a degenerate level as
+    many times as its multiplicity (up to n_block, more with the restarts of a
+    nearly singular overlap), standard Lanczos only once; the values follow
+    the seniority closed form."""
+    G = 0.37
+    b = ob.build_basis((two_j,), n, 0, two_M)
+    H = oh.dense_h(b, _pairing_interaction(two_j, G))
+    omega = (two_j + 1) // 2
+    levels = []
+    for v in range(n % 2, min(n, 2 * omega - n) + 1, 2):
+        mult = _sd_count(two_j, v, two_M) - _sd_count(two_j, v - 2, two_M)
+        levels.append((-(G / 4.0) * (n - v) * (2 * omega - n - v + 2), mult))
+    levels.sort()
+    expect = np.concatenate([[e] * m for e, m in levels])
+    n_low = min(levels[0][1] + levels[1][1], 6)   # the two lowest levels, with multiplicity
+    assert levels[1][1] > 1
+    rng = np.random.default_rng(5)
+    got, _, _, _ = ol.block_lanczos(lambda X: H @ X, rng.standard_normal((b.dim, nb)), 20, 6)
+    assert np.allclose(got[:n_low], expect[:n_low], atol=1e-12)
+    assert np.all(got >= expect[:len(got)] - 1e-10)   # Ritz values interlace from above
+    one, _, _, _ = ol.block_lanczos(lambda X: H @ X, rng.standard_normal((b.dim, 1)), 20, 6)
+    assert len(one) < 6 and np.allclose(one, [e for e, _ in levels][:len(one)], atol=1e-12)
+
+
 # ------------------------------------------ one-body transition densities
 def _random_pair(b, seed):
     rng = np.random.default_rng(seed)
