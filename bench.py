@@ -39,7 +39,7 @@ def kernel_source_hash():
     code, table builder, shared layout constants): stored PMC traffic is used
     only for exactly these sources."""
     h = hashlib.sha256()
-    for f in ("kernels_tiled.hip", "host_ham.cpp", "fotci_internal.h"):
+    for f in ("kernels_tiled.hip", "tiled_common.h", "host_ham.cpp", "fotci_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1801_08432_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -160,6 +160,57 @@ def density_leg(h, w, reps=5):
     return dict(ms=round(1e3 * t, 4), streamed_bytes=nbytes, achieved_gbs=round(nbytes / t / 1e9, 1))
 
 
+def block_leg(h, mode, steps, one_vector_ms, nbs=(2, 4, 8)):
+    """Block apply_H (blocks of n_b vectors stored row-wise): mean time per
+    block apply and per kernel from HIP events, apply_H/s counted per vector,
+    and the speed-up per vector over the one-vector apply."""
+    import torch
+    dt = torch.float64 if mode.startswith("f64") else torch.float32
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(1803)
+    res = {}
+    for nb in nbs:
+        X = torch.randn(h.dim, nb, dtype=dt, device="cuda:0", generator=gen)
+        Y = torch.empty_like(X)
+        for _ in range(2):
+            h.apply_block(X, Y, mode=mode)
+        torch.cuda.synchronize()
+        h.profile_start(steps)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h.apply_block(X, Y, mode=mode)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        kms, _ = h.profile_stop()
+        res[str(nb)] = dict(ms_per_block_apply=round(1e3 * t, 4), apply_H_per_s=round(nb / t, 2),
+                            speedup_per_vector=round(one_vector_ms / (1e3 * t / nb), 3),
+                            kernels_ms={k: round(v, 4) for k, v in kms.items()})
+        log("[bench] block apply n_b=%d: %s" % (nb, res[str(nb)]))
+        del X, Y
+    return dict(mode=mode, layout="row-wise (vector index fastest)", by_n_block=res)
+
+
+def block_lanczos_leg(h, mode, n_block, n_iter, ref=None):
+    """Block Lanczos from a seeded block: time per block iteration and per
+    Krylov vector, residuals, and the lowest eigenvalues against a reference
+    run when given."""
+    import torch
+    from paper_1801_08432_amd import inputs
+    piv = torch.from_numpy(np.random.default_rng(1804).standard_normal((h.dim, n_block))).to("cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = h.lanczos_block(piv, 10, n_iter, mode=mode)
+    t = time.perf_counter() - t0
+    out = dict(mode=mode, n_block=n_block, n_iter=n_iter, blocks_done=r["n_done"], seconds=round(t, 3),
+               s_per_block_iter=round(t / max(r["n_done"], 1), 5),
+               s_per_vector=round(t / max(r["n_done"] * n_block, 1), 6),
+               resid=[float("%.3g" % v) for v in r["resid"]], workspace_gb=round(r["workspace_bytes"] / 1e9, 2))
+    if ref is not None:
+        out["rel_diff_vs_standard_f64_plain"] = [float("%.3g" % v) for v in np.abs(r["evals"] - ref) / np.abs(ref)]
+    log("[bench] block lanczos: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +224,8 @@ def main():
     ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--no-trlan", action="store_true")
     ap.add_argument("--no-jcoupled", action="store_true")
+    ap.add_argument("--no-block", action="store_true")
+    ap.add_argument("--block-iters", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 1 GiB (float32) once, a known-size kernel for HBM counter calibration")
@@ -313,6 +366,10 @@ def main():
                                                                        np.abs(ref[:5])))
         out["thick_restart"] = tr
         log("[bench] thick restart: %s" % tr)
+    if not a.no_block:
+        out["block"] = block_leg(h, mode, a.steps, 1e3 * t_wall / a.steps)
+        ref = res["f64_plain"][0]["evals"] if "lanczos" in out else None
+        out["block"]["lanczos"] = block_lanczos_leg(h, mode, 4, a.block_iters, ref)
     if not a.no_density:
         out["one_body_density"] = density_leg(h, w)
     if not a.no_jcoupled:

@@ -198,6 +198,24 @@ int fotci_ham_upload(fotci_ham *h, void *dev_workspace, int64_t bytes, void *str
 int fotci_apply_H(const fotci_ham *h, int32_t mode, const void *x, void *y, void *stream);
 
 /*
+ * fotci_apply_H_block -- Y = H X for a block of n_block vectors stored
+ * row-wise (Ch. "Block Lanczos": the Hamiltonian applied to a block whose
+ * vectors are adjacent in memory element by element, so every matrix element
+ * reconstructed serves the whole block). X, Y: device arrays of dim * n_block
+ * elements, element i of vector v at [i * n_block + v] (a row-major
+ * dim x n_block matrix), float64 for FOTCI_MODE_F64 and float32 for
+ * FOTCI_MODE_F32, 16-byte aligned, not overlapping; Y is overwritten.
+ * n_block: 1, 2, 4 or 8 (1 is fotci_apply_H, which also takes
+ * FOTCI_MODE_F64_PLAIN). Each vector's result is fotci_apply_H of that vector
+ * with the same per-element arithmetic. FOTCI_EINVAL for another n_block,
+ * FOTCI_MODE_F64_PLAIN with n_block > 1, misaligned pointers, a block of more
+ * than 2^31 - 2^20 bytes (32-bit buffer offsets), or sectors too large for
+ * the kernels' LDS tiles; FOTCI_ESTATE if the Hamiltonian is not uploaded.
+ * Asynchronous on `stream`; fotci_profile_start records its kernels too.
+ */
+int fotci_apply_H_block(const fotci_ham *h, int32_t mode, int32_t n_block, const void *x, void *y, void *stream);
+
+/*
  * fotci_one_body_density -- m-scheme one-body transition densities of two
  * vectors of the basis (Ch. 5, "One-body density matrices", in the
  * proton-neutron form the reduced densities are coupled from):
@@ -292,6 +310,51 @@ int64_t fotci_trlan_workspace_bytes(const fotci_ham *h, const fotci_trlan_opts *
 int fotci_lanczos_thick_restart(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, void *work,
                                 int64_t work_bytes, double *evals, double *resid, double *evecs, int32_t *stats,
                                 void *stream);
+
+/*
+ * Block Lanczos (Ch. "Block Lanczos"): H V_n = V_{n-1} B_{n-1}^T + V_n A_n +
+ * V_{n+1} B_n for blocks V_n of n_block orthonormal vectors. Per block
+ * iteration: W = H V_n (fotci_apply_H_block); A_n = V_n^T W;
+ * W -= V_n A_n + V_{n-1} B_{n-1}^T; classical Gram-Schmidt of W against every
+ * block so far, twice (float64 sums); the overlap W^T W = U Lambda U^T gives
+ * B_n = Lambda^{1/2} U^T and V_{n+1} = W U Lambda^{-1/2} (repeated once on
+ * the new block, B_n the product of both factors). The block-tridiagonal
+ * matrix of the A_n and B_n is diagonalised on the host in float64 (Jacobi
+ * rotations); Ritz vectors and refinement as in fotci_lanczos_lowest. Blocks
+ * are stored row-wise in the mode's precision; W and every sum are float64.
+ */
+typedef struct {
+    int32_t n_keep;   /* lowest eigenpairs wanted, 1..16 */
+    int32_t n_block;  /* vectors per block: 1, 2, 4 or 8 */
+    int32_t n_iter;   /* block iterations, >= 1, with n_iter * n_block <= 4096 */
+    int32_t mode;     /* FOTCI_MODE_F64 or FOTCI_MODE_F32 */
+    int32_t refine;   /* 1: float64 Rayleigh-quotient refinement of the Ritz vectors */
+} fotci_block_lanczos_opts;
+
+/* Bytes of device workspace fotci_lanczos_block needs (negative error code
+ * for invalid options). */
+int64_t fotci_block_lanczos_workspace_bytes(const fotci_ham *h, const fotci_block_lanczos_opts *o);
+
+/*
+ * pivot: device float64 [dim * n_block], the starting block, row-wise as in
+ * fotci_apply_H_block, 16-byte aligned (orthonormalised internally;
+ * FOTCI_EINVAL if its columns are linearly dependent). work: device
+ * workspace (256-byte aligned) of at least the queried size. evals, resid:
+ * host [n_keep]; evecs: device float64 [n_keep*dim] Ritz vectors (one after
+ * another, unit norm) or NULL; n_done: host, the block iterations carried
+ * out, or NULL. A column of a new block whose overlap eigenvalue has
+ * sqrt(lambda) <= 1e-7 times the norm of the block-tridiagonal matrix
+ * (dependent on the basis to the resolution of the overlap) is replaced by a
+ * new vector: the basis vector e_k, k = ((r * n_block + column) * 2654435761)
+ * mod dim at the r-th replacement of the run, orthogonalised against the
+ * basis. The iteration stops early when every column of a new block is
+ * dependent (the block Krylov space is invariant to rounding) or a new vector
+ * lies in the span. Synchronous. FOTCI_ENOTCONV if fewer than n_keep Ritz
+ * values exist.
+ */
+int fotci_lanczos_block(const fotci_ham *h, const fotci_block_lanczos_opts *o, const double *pivot, void *work,
+                        int64_t work_bytes, double *evals, double *resid, double *evecs, int32_t *n_done,
+                        void *stream);
 
 /* Counts of the work in one apply_H (host; no device needed): multiply-adds
  * of the pp, nn and pn parts and of the diagonal, as the paper counts

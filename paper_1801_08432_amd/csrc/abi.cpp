@@ -175,6 +175,23 @@ int fotci_apply_H(const fotci_ham *h, int32_t mode, const void *x, void *y, void
     });
 }
 
+int fotci_apply_H_block(const fotci_ham *h, int32_t mode, int32_t n_block, const void *x, void *y, void *stream) {
+    return guard([&] {
+        if (!h || !x || !y) fail(FOTCI_EINVAL, "NULL argument");
+        if (n_block != 1 && n_block != 2 && n_block != 4 && n_block != 8)
+            fail(FOTCI_EINVAL, "n_block must be 1, 2, 4 or 8");
+        if (mode != FOTCI_MODE_F64 && mode != FOTCI_MODE_F32 && !(mode == FOTCI_MODE_F64_PLAIN && n_block == 1))
+            fail(FOTCI_EINVAL, "block apply_H needs FOTCI_MODE_F64 or FOTCI_MODE_F32");
+        if (!h->uploaded) fail(FOTCI_ESTATE, "Hamiltonian not uploaded");
+        const int64_t es = mode == FOTCI_MODE_F32 ? 4 : 8;
+        const int64_t bytes = h->j->b->dim * n_block * es;
+        const char *xa = (const char *)x, *ya = (const char *)y;
+        if (xa < ya + bytes && ya < xa + bytes) fail(FOTCI_EINVAL, "x and y must not overlap");
+        launch_apply_nb(h, mode, n_block, x, y, stream);
+        return FOTCI_OK;
+    });
+}
+
 int fotci_apply_H_vjp(const fotci_ham *h, const double *x, const double *g, double *dx, double *d_spe_p,
                       double *d_spe_n, double *d_v_pp, double *d_v_nn, double *d_v_pn, void *stream) {
     return guard([&] {
@@ -239,6 +256,27 @@ int fotci_lanczos_thick_restart(const fotci_ham *h, const fotci_trlan_opts *o, c
         if (!h || !o || !pivot || !work || !evals || !resid) fail(FOTCI_EINVAL, "NULL argument");
         if (!h->uploaded) fail(FOTCI_ESTATE, "Hamiltonian not uploaded");
         trlan_run(h, o, pivot, work, work_bytes, evals, resid, evecs, stats, stream);
+        return FOTCI_OK;
+    });
+}
+
+int64_t fotci_block_lanczos_workspace_bytes(const fotci_ham *h, const fotci_block_lanczos_opts *o) {
+    int64_t r = 0;
+    int rc = guard([&] {
+        if (!h || !o) fail(FOTCI_EINVAL, "NULL argument");
+        r = block_lanczos_bytes(h, o);
+        return FOTCI_OK;
+    });
+    return rc == FOTCI_OK ? r : rc;
+}
+
+int fotci_lanczos_block(const fotci_ham *h, const fotci_block_lanczos_opts *o, const double *pivot, void *work,
+                        int64_t work_bytes, double *evals, double *resid, double *evecs, int32_t *n_done,
+                        void *stream) {
+    return guard([&] {
+        if (!h || !o || !pivot || !work || !evals || !resid) fail(FOTCI_EINVAL, "NULL argument");
+        if (!h->uploaded) fail(FOTCI_ESTATE, "Hamiltonian not uploaded");
+        block_lanczos_run(h, o, pivot, work, work_bytes, evals, resid, evecs, n_done, stream);
         return FOTCI_OK;
     });
 }

@@ -250,6 +250,10 @@ void launch_apply(const fotci_ham *h, int mode, const void *x, void *y, void *st
 void launch_apply_plain(const DevHam &d, int mode, const void *x, void *y, void *stream);
 void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream,
                         void **events = nullptr);
+void launch_apply_block(const DevHam &d, const DevTiled &t, int mode, int nb, const void *x, void *y, void *stream,
+                        void **events = nullptr);
+// block apply with the per-kernel timing of launch_apply; nb == 1 is launch_apply
+void launch_apply_nb(const fotci_ham *h, int mode, int nb, const void *x, void *y, void *stream);
 void build_tiled_tables(fotci_ham *h);
 void launch_one_body_density(const DevHam &d, const std::vector<int32_t> &h_sec_np, int q0, const double *g,
                              const double *x, double *rho_p, double *rho_n, void *stream);
@@ -263,6 +267,10 @@ void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *
 int64_t trlan_bytes(const fotci_ham *h, const fotci_trlan_opts *o);
 void trlan_run(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, void *work, int64_t work_bytes,
                double *evals, double *resid, double *evecs, int32_t *stats, void *stream);
+int64_t block_lanczos_bytes(const fotci_ham *h, const fotci_block_lanczos_opts *o);
+void block_lanczos_run(const fotci_ham *h, const fotci_block_lanczos_opts *o, const double *pivot, void *work,
+                       int64_t work_bytes, double *evals, double *resid, double *evecs, int32_t *n_done,
+                       void *stream);
 void hip_check(int err, const char *what);
 
 // tridiagonal symmetric eigenproblem (host, float64): implicit QL with

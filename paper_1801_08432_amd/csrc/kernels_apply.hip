@@ -186,4 +186,22 @@ void launch_apply(const fotci_ham *h, int mode, const void *x, void *y, void *st
     if (ev) pr.calls++;
 }
 
+void launch_apply_nb(const fotci_ham *h, int mode, int nb, const void *x, void *y, void *stream) {
+    if (nb == 1) {
+        launch_apply(h, mode, x, y, stream);
+        return;
+    }
+    auto &pr = h->prof;
+    void **ev = nullptr;
+    if (pr.on && pr.calls < pr.max_calls) ev = &pr.events[(size_t)pr.calls * 5];
+    launch_apply_block(h->dev, h->dev_tiled, mode, nb, x, y, stream, ev);
+    if (ev) {
+        pr.n_kernels = 3;
+        pr.names[0] = "k_nn_diag_blk";
+        pr.names[1] = "k_pp_blk";
+        pr.names[2] = "k_pn_blk";
+        pr.calls++;
+    }
+}
+
 }  // namespace fotci

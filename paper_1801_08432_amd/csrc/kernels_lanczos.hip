@@ -336,6 +336,204 @@ __global__ __launch_bounds__(kThreads) void k_resid_partial(const double *__rest
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// ------------------------------------------------------------ block Lanczos
+// Blocks of NB vectors are stored row-wise, as the block apply_H takes them:
+// row i of block j at V[j * ldb + i * NB + v] with ldb = ld * NB. A workgroup
+// owns kThreads * brows rows; thread t owns rows r0 + q * kThreads + t
+// (q < brows), so one load instruction of a wave reads 64 consecutive rows.
+// brows shrinks as the NB x NB float64 accumulators grow (no spills).
+constexpr int brows_of(int nb) { return nb <= 2 ? 8 : (nb == 4 ? 4 : 2); }
+template <int NB>
+constexpr int brows() {
+    return brows_of(NB);
+}
+template <int NB>
+constexpr int bchunk() {
+    return kThreads * brows<NB>();
+}
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// Row i of a row-wise block, widened to float64 (zero for i >= n).
+template <typename T, int NB>
+__device__ __forceinline__ void load_brow(const T *__restrict__ base, int64_t i, int64_t n, double (&out)[NB]) {
+    if (i < n) {
+        const T *p = base + i * NB;
+        if constexpr (NB * sizeof(T) >= 16) {
+            constexpr int NV = 16 / (int)sizeof(T);
+            typedef typename Vec16<T>::type VT;
+#pragma unroll
+            for (int q = 0; q < NB / NV; ++q) {
+                const VT t = *(const VT *)(p + q * NV);
+                const T *tp = (const T *)&t;
+#pragma unroll
+                for (int e = 0; e < NV; ++e) out[q * NV + e] = (double)tp[e];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NB; ++v) out[v] = (double)p[v];
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NB; ++v) out[v] = 0.0;
+    }
+}
+
+// Sums each of the NQ values of every lane over the wave (NQ a power of two
+// up to 64): each step exchanges half of the values a lane still holds with
+// the lane `o` apart and keeps the other half, so the values are spread over
+// the lanes with log2(NQ) steps and NQ - 1 exchanges; plain exchanges finish
+// the sums. Lane l returns the total of value l >> (6 - log2 NQ).
+template <int NQ, int ST>
+__device__ __forceinline__ void spread_step(double (&a)[NQ], int lane) {
+    if constexpr ((NQ >> ST) > 1) {
+        constexpr int half = (NQ >> ST) / 2, o = 32 >> ST;
+        const bool hi = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double keep = hi ? a[i + half] : a[i];
+            const double give = hi ? a[i] : a[i + half];
+            a[i] = keep + __shfl_xor(give, o, 64);
+        }
+        spread_step<NQ, ST + 1>(a, lane);
+    }
+}
+
+template <int NQ>
+__device__ __forceinline__ double wave_sum_spread(double (&a)[NQ]) {
+    constexpr int LOG = ilog2(NQ);
+    spread_step<NQ, 0>(a, threadIdx.x & 63);
+    double v = a[0];
+#pragma unroll
+    for (int o = 32 >> LOG; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// partial[(j*NB*NB + v*NB + u) * nb + block] = sum over the block's rows of
+// V_j[i, v] W[i, u] for j < k: the workgroup's share of V_j^T W.
+template <typename TV, int NB>
+__global__ __launch_bounds__(kThreads) void k_bmultidot(const TV *__restrict__ V, int64_t ldb, int k,
+                                                        const double *__restrict__ W, int64_t n,
+                                                        double *__restrict__ partial) {
+    constexpr int NQ = NB * NB, RPT = brows<NB>(), LOG = ilog2(NQ);
+    __shared__ double lds[2][kWaves][NQ];
+    const int64_t r0 = (int64_t)blockIdx.x * bchunk<NB>() + threadIdx.x;
+    const int nb = gridDim.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double wr[RPT][NB];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) load_brow<double, NB>(W, r0 + (int64_t)q * kThreads, n, wr[q]);
+    for (int j = 0; j < k; ++j) {
+        const TV *Vj = V + (int64_t)j * ldb;
+        double acc[NQ];
+#pragma unroll
+        for (int e = 0; e < NQ; ++e) acc[e] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            double vr[NB];
+            load_brow<TV, NB>(Vj, r0 + (int64_t)q * kThreads, n, vr);
+#pragma unroll
+            for (int v = 0; v < NB; ++v)
+#pragma unroll
+                for (int u = 0; u < NB; ++u) acc[v * NB + u] += vr[v] * wr[q][u];
+        }
+        const double t = wave_sum_spread<NQ>(acc);
+        // double-buffered: the readers of j - 1 passed this barrier's
+        // predecessor before anyone writes the same buffer at j + 1
+        if ((lane & ((64 >> LOG) - 1)) == 0) lds[j & 1][wid][lane >> (6 - LOG)] = t;
+        __syncthreads();
+        if (threadIdx.x < NQ) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) sum += lds[j & 1][w][threadIdx.x];
+            partial[((int64_t)j * NQ + threadIdx.x) * nb + blockIdx.x] = sum;
+        }
+    }
+}
+
+// W[i, u] -= sum_{j < k} sum_v V_j[i, v] C[(j*NB + v)*NB + u].
+template <typename TV, int NB>
+__global__ __launch_bounds__(kThreads) void k_bsubtract(const TV *__restrict__ V, int64_t ldb, int k,
+                                                        const double *__restrict__ C, double *__restrict__ W,
+                                                        int64_t n) {
+    constexpr int RPT = brows<NB>();
+    const int64_t r0 = (int64_t)blockIdx.x * bchunk<NB>() + threadIdx.x;
+    double acc[RPT][NB];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[q][u] = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const TV *Vj = V + (int64_t)j * ldb;
+        const double *Cj = C + (int64_t)j * NB * NB;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            double vr[NB];
+            load_brow<TV, NB>(Vj, r0 + (int64_t)q * kThreads, n, vr);
+#pragma unroll
+            for (int v = 0; v < NB; ++v)
+#pragma unroll
+                for (int u = 0; u < NB; ++u) acc[q][u] += vr[v] * Cj[v * NB + u];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = r0 + (int64_t)q * kThreads;
+        if (i < n) {
+            double *wp = W + i * NB;
+#pragma unroll
+            for (int u = 0; u < NB; ++u) wp[u] -= acc[q][u];
+        }
+    }
+}
+
+// out[i, u] = sum_v W[i, v] M[v*NB + u] (float64 sums, stored as TO); out may
+// be W itself (each thread reads its row whole before writing it).
+template <typename TO, int NB>
+__global__ __launch_bounds__(kThreads) void k_bmix(const double *W, const double *__restrict__ M, TO *out,
+                                                   int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        double w[NB];
+        load_brow<double, NB>(W, i, n, w);
+        TO *op = out + i * NB;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            double t = 0.0;
+#pragma unroll
+            for (int v = 0; v < NB; ++v) t += w[v] * M[v * NB + u];
+            op[u] = (TO)t;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_widen(const T *__restrict__ a, double *__restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        b[i] = (double)a[i];
+}
+
+// Y_c[i] = sum_{j < k} sum_v V_j[i, v] S[(j*NB + v)*s_ld + c0 + c] for c < nc
+// <= 16 (float64 sums): Ritz vectors from a row-wise block basis, stored one
+// after another (row stride n).
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void k_britz(const T *__restrict__ V, int64_t ldb, int k,
+                                                    const double *__restrict__ S, int s_ld, int c0, int nc,
+                                                    double *__restrict__ Y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    double acc[16];
+    for (int c = 0; c < nc; ++c) acc[c] = 0.0;
+    for (int j = 0; j < k; ++j) {
+        double vr[NB];
+        load_brow<T, NB>(V + (int64_t)j * ldb, i, n, vr);
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const double *Sr = S + (int64_t)(j * NB + v) * s_ld + c0;
+            for (int c = 0; c < nc; ++c) acc[c] += vr[v] * Sr[c];
+        }
+    }
+    for (int c = 0; c < nc; ++c) Y[(int64_t)c * n + i] = acc[c];
+}
+
 int stream_blocks(int64_t n) {
     int64_t b = (n + kThreads - 1) / kThreads;
     return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
@@ -393,6 +591,43 @@ Layout standard_layout(const fotci_ham *h, const fotci_lanczos_opts *o) {
 Layout trlan_layout(const fotci_ham *h, const fotci_trlan_opts *o) {
     return make_layout(h->j->b->dim, elem_size(o->mode), o->n_basis + 1, o->n_thick, o->n_basis + 1,
                        std::max(o->n_thick, o->n_keep), o->n_keep);
+}
+
+// Block Lanczos: n_iter + 1 row-wise blocks, the block H V_n (mode precision)
+// and its float64 copy W, partial sums of the block kernels, coefficients
+// (Gram-Schmidt for every block, three-term, mixing and overlap matrices).
+Layout block_layout(const fotci_ham *h, const fotci_block_lanczos_opts *o) {
+    const int64_t dim = h->j->b->dim;
+    const int nb = o->n_block, es = elem_size(o->mode);
+    const int nblk = o->n_iter + 1, nq = nb * nb;
+    const int64_t chunk = (int64_t)kThreads * brows_of(nb);   // bchunk<NB>()
+    const int64_t nbc = std::max<int64_t>((dim + chunk - 1) / chunk, 2048);
+    Layout L{};
+    L.ld = (dim + 63) & ~(int64_t)63;
+    int64_t off = 0;
+    L.basis = off;
+    off = a256(off + (int64_t)nblk * L.ld * nb * es);
+    L.scratch = off;
+    L.y = off;
+    off = a256(off + dim * nb * es);
+    L.w = off;
+    off = a256(off + dim * nb * 8);
+    L.partial = off;
+    off = a256(off + (int64_t)nblk * nq * nbc * 8);
+    L.sq = off;
+    off = a256(off + nbc * 8);
+    L.scal = off;
+    off = a256(off + 64 * 8);
+    L.coef = off;
+    off = a256(off + (int64_t)(nblk + 4) * nq * 8);
+    L.S = off;
+    off = a256(off + (int64_t)o->n_iter * nb * o->n_keep * 8);
+    L.ritz = off;
+    off = a256(off + (int64_t)o->n_keep * dim * 8);
+    L.hy = off;
+    off = a256(off + dim * 8);
+    L.total = off;
+    return L;
 }
 
 // Device state and the steps shared by the standard and thick-restart drivers.
@@ -519,6 +754,13 @@ struct Lz {
         for (int l = 0; l < m; ++l)
             for (int j = 0; j < nk; ++j) S[(size_t)l * nk + j] = z[(size_t)l * m + j];
         combine<double>(m, S, nk, nk, ritz, dim);
+        finish_ritz(theta, nk, refine, evals, resid);
+    }
+
+    // The nk Ritz vectors in ritz (float64, one after another): normalised;
+    // theta[j] replaced by the float64 Rayleigh quotient when refining;
+    // resid[j] = ||H y - theta y||.
+    void finish_ritz(const std::vector<double> &theta, int nk, bool refine, double *evals, double *resid) {
         for (int j = 0; j < nk; ++j) {
             double *yj = ritz + (int64_t)j * dim;
             dot_into((const double *)yj, (const double *)yj, scal + 2, 1);
@@ -655,6 +897,263 @@ void run_trlan(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivo
     }
 }
 
+// Block Lanczos (Ch. "Block Lanczos"): H V_n = V_{n-1} B_{n-1}^T + V_n A_n +
+// V_{n+1} B_n. Per block iteration: W = H V_n (block apply_H, widened to
+// float64); A_n = V_n^T W, taken first as alpha is in the one-vector driver;
+// W -= V_n A_n + V_{n-1} B_{n-1}^T; classical Gram-Schmidt against blocks
+// 0..n, twice. The overlap O = W^T W = U Lambda U^T of the residual block
+// gives B_n = Lambda^{1/2} U^T and V_{n+1} = W U Lambda^{-1/2}; the
+// factorisation is repeated once on the new block (whose overlap is the
+// identity to rounding) and B_n is the product of the two factors. Nearly
+// dependent columns are replaced by new vectors (next_block); the iteration
+// stops when the whole block is dependent on the basis. The block-tridiagonal
+// T is diagonalised on the host.
+template <typename T, int NB>
+struct BlockRun {
+    static constexpr int NQ = NB * NB;
+    Lz<T> &z;
+    hipStream_t st;
+    int64_t dim, ldb;
+    int gb, sbn;
+    double *cg, *c3, *cm, *co;   // coefficient slots, see block_layout
+
+    BlockRun(Lz<T> &z_, int n_iter)
+        : z(z_), st(z_.st), dim(z_.dim), ldb(z_.ld * NB), gb((int)((z_.dim + bchunk<NB>() - 1) / bchunk<NB>())),
+          sbn(stream_blocks(z_.dim)) {
+        cg = z.coef;
+        c3 = cg + (int64_t)(n_iter + 1) * NQ;
+        cm = c3 + 2 * NQ;
+        co = cm + NQ;
+    }
+
+    T *blk(int j) const { return z.basis + (int64_t)j * ldb; }
+
+    // out[k*NQ] = V_j^T W for blocks 0..k-1 of V
+    template <typename TV>
+    void multidot(const TV *V, int64_t ld_v, int k, double *out) {
+        hipLaunchKernelGGL((k_bmultidot<TV, NB>), dim3(gb), dim3(kThreads), 0, st, V, ld_v, k, (const double *)z.w,
+                           dim, z.partial);
+        hipLaunchKernelGGL(k_reduce_rows, dim3(k * NQ), dim3(kThreads), 0, st, (const double *)z.partial, gb, out);
+    }
+
+    // W -= sum_{j < k} V_{j0+j} C_j
+    void subtract(int j0, int k, const double *C) {
+        hipLaunchKernelGGL((k_bsubtract<T, NB>), dim3(gb), dim3(kThreads), 0, st, (const T *)blk(j0), ldb, k, C,
+                           z.w, dim);
+    }
+
+    void to_host(double *host, const double *dev, int n) {
+        hip_check(hipMemcpyAsync(host, dev, (size_t)n * 8, hipMemcpyDeviceToHost, st), "block copy");
+    }
+    void to_dev(double *dev, const double *host, int n) {
+        hip_check(hipMemcpyAsync(dev, host, (size_t)n * 8, hipMemcpyHostToDevice, st), "block copy");
+    }
+
+    // O = W^T W on the host, exactly symmetric
+    void overlap(std::vector<double> &O) {
+        multidot<double>(z.w, 0, 1, co);
+        O.assign(NQ, 0.0);
+        to_host(O.data(), co, NQ);
+        hip_check(hipStreamSynchronize(st), "block sync");
+        for (int a = 0; a < NB; ++a)
+            for (int b = 0; b < a; ++b) O[a * NB + b] = O[b * NB + a] = 0.5 * (O[a * NB + b] + O[b * NB + a]);
+    }
+
+    // O = U Lambda U^T: M = U Lambda^{-1/2}, B = Lambda^{1/2} U^T
+    static void factor(const std::vector<double> &O, std::vector<double> &M, std::vector<double> &B, double &lmin,
+                       double &lmax) {
+        std::vector<double> lam, U;
+        sym_eig(NB, O, lam, U);
+        lmin = lam[0];
+        lmax = lam[NB - 1];
+        M.assign(NQ, 0.0);
+        B.assign(NQ, 0.0);
+        for (int v = 0; v < NB; ++v)
+            for (int u = 0; u < NB; ++u) M[v * NB + u] = lam[u] > 0.0 ? U[v * NB + u] / std::sqrt(lam[u]) : 0.0;
+        for (int a = 0; a < NB; ++a)
+            for (int b = 0; b < NB; ++b) B[a * NB + b] = std::sqrt(std::max(lam[a], 0.0)) * U[b * NB + a];
+    }
+
+    // W (float64, unit-norm columns after the first mixing) -> block dst,
+    // second factorisation; B = B2 * B1. False if an overlap eigenvalue is
+    // <= floor.
+    bool finish_block(int dst, const std::vector<double> &B1, double floor, std::vector<double> &B) {
+        std::vector<double> O, M2, B2;
+        double lmin, lmax;
+        overlap(O);   // synchronises: earlier mixing has read cm
+        factor(O, M2, B2, lmin, lmax);
+        if (!(lmin > floor)) return false;
+        to_dev(cm, M2.data(), NQ);
+        hipLaunchKernelGGL((k_bmix<T, NB>), dim3(sbn), dim3(kThreads), 0, st, (const double *)z.w,
+                           (const double *)cm, blk(dst), dim);
+        B.assign(NQ, 0.0);
+        for (int a = 0; a < NB; ++a)
+            for (int c = 0; c < NB; ++c) {
+                double t = 0.0;
+                for (int b = 0; b < NB; ++b) t += B2[a * NB + b] * B1[b * NB + c];
+                B[a * NB + c] = t;
+            }
+        hip_check(hipGetLastError(), "block launch");
+        return true;
+    }
+
+    void mix_in_place(const std::vector<double> &M) {
+        to_dev(cm, M.data(), NQ);
+        hipLaunchKernelGGL((k_bmix<double, NB>), dim3(sbn), dim3(kThreads), 0, st, (const double *)z.w,
+                           (const double *)cm, z.w, dim);
+    }
+
+    // The pivot block (in W) -> V_0; false if its columns are dependent.
+    bool first_block() {
+        std::vector<double> O, M1, B1, B;
+        double lmin, lmax;
+        overlap(O);
+        factor(O, M1, B1, lmin, lmax);
+        if (!(lmin > 1e-24 * lmax)) return false;
+        mix_in_place(M1);
+        return finish_block(0, B1, 0.0, B);
+    }
+
+    // The residual block W -> V_dst with W ~= V_dst B. A column whose overlap
+    // eigenvalue has sqrt(lambda) <= 1e-7 ||T|| (the resolution of a Gram
+    // matrix is about sqrt(eps) of the block's norm) is replaced by the basis
+    // vector e_k, k = ((fills * NB + u) * 2654435761) mod dim, with a zero row
+    // of B; after a replacement, or when a kept column has sqrt(lambda) <
+    // 1e-4 ||T||, the block is orthogonalised against blocks 0..dst-1 again
+    // (twice) before the second factorisation. False when every column is
+    // dependent or the refreshed block has an overlap eigenvalue <= 1e-12.
+    bool next_block(double tnorm, int dst, int &fills, std::vector<double> &B) {
+        std::vector<double> O, lam, U;
+        overlap(O);
+        sym_eig(NB, O, lam, U);
+        std::vector<double> M1(NQ, 0.0), B1(NQ, 0.0);
+        int nbad = 0;
+        double weakest = INFINITY;
+        for (int u = 0; u < NB; ++u) {
+            const double root = std::sqrt(std::max(lam[u], 0.0));
+            if (root <= 1e-7 * tnorm) {
+                ++nbad;
+                continue;
+            }
+            weakest = std::min(weakest, root);
+            for (int v = 0; v < NB; ++v) {
+                M1[v * NB + u] = U[v * NB + u] / root;
+                B1[u * NB + v] = root * U[v * NB + u];
+            }
+        }
+        if (nbad == NB) return false;
+        mix_in_place(M1);
+        if (nbad > 0) {
+            static const double one = 1.0;
+            for (int u = 0; u < NB; ++u) {
+                if (std::sqrt(std::max(lam[u], 0.0)) > 1e-7 * tnorm) continue;
+                const uint64_t k = ((uint64_t)(fills * NB + u) * 2654435761ull) % (uint64_t)dim;
+                hip_check(hipMemcpyAsync(z.w + k * NB + u, &one, 8, hipMemcpyHostToDevice, st), "restart vector");
+            }
+            ++fills;
+        }
+        if (nbad > 0 || weakest < 1e-4 * tnorm)
+            for (int pass = 0; pass < 2; ++pass) {
+                multidot<T>(blk(0), ldb, dst, cg);
+                subtract(0, dst, cg);
+            }
+        return finish_block(dst, B1, 1e-12, B);
+    }
+};
+
+double frob(const std::vector<double> &a) {
+    double s = 0.0;
+    for (double x : a) s += x * x;
+    return std::sqrt(s);
+}
+
+template <typename T, int NB>
+void run_block(const fotci_ham *h, const fotci_block_lanczos_opts *o, const double *pivot, char *work,
+               double *evals, double *resid, double *evecs, int32_t *n_done, hipStream_t st) {
+    constexpr int NQ = NB * NB;
+    Lz<T> z(h, block_layout(h, o), o->mode, FOTCI_REORTH_CGS2, work, evecs, st);
+    BlockRun<T, NB> b(z, o->n_iter);
+    const int64_t dim = z.dim;
+    // V_0 from the pivot block
+    hip_check(hipMemcpyAsync(z.w, pivot, (size_t)dim * NB * 8, hipMemcpyDeviceToDevice, st), "pivot copy");
+    if (!b.first_block()) fail(FOTCI_EINVAL, "pivot block columns are linearly dependent");
+    std::vector<std::vector<double>> As, Bs;
+    double tnorm = 0.0;
+    int done = 0, fills = 0;
+    for (int n = 0; n < o->n_iter; ++n) {
+        launch_apply_nb(h, z.mode, NB, b.blk(n), z.y, st);
+        hipLaunchKernelGGL(k_widen<T>, dim3(stream_blocks(dim * NB)), dim3(kThreads), 0, st, (const T *)z.y, z.w,
+                           dim * NB);
+        b.template multidot<T>(b.blk(n), b.ldb, 1, b.c3 + NQ);   // A_n
+        if (n > 0) {
+            std::vector<double> Bt(NQ);
+            for (int v = 0; v < NB; ++v)
+                for (int u = 0; u < NB; ++u) Bt[v * NB + u] = Bs[n - 1][u * NB + v];
+            b.to_dev(b.c3, Bt.data(), NQ);
+            b.subtract(n - 1, 2, b.c3);   // blocks n-1, n: coefficients B_{n-1}^T, A_n
+        } else {
+            b.subtract(0, 1, b.c3 + NQ);
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            b.template multidot<T>(b.blk(0), b.ldb, n + 1, b.cg);
+            b.subtract(0, n + 1, b.cg);
+        }
+        std::vector<double> A(NQ);
+        b.to_host(A.data(), b.c3 + NQ, NQ);
+        hip_check(hipStreamSynchronize(st), "block sync");
+        for (int v = 0; v < NB; ++v)
+            for (int u = 0; u < v; ++u) A[v * NB + u] = A[u * NB + v] = 0.5 * (A[v * NB + u] + A[u * NB + v]);
+        As.push_back(A);
+        done = n + 1;
+        if (n == o->n_iter - 1) break;
+        const double side = n > 0 ? frob(Bs[n - 1]) : 0.0;
+        tnorm = std::max(tnorm, frob(A) + side);
+        std::vector<double> Bn;
+        if (!b.next_block(tnorm, n + 1, fills, Bn)) break;   // invariant block Krylov space
+        Bs.push_back(Bn);
+        tnorm = std::max(tnorm, frob(A) + side + frob(Bn));
+    }
+    const int m = done * NB;
+    if (m < o->n_keep) fail(FOTCI_ENOTCONV, "block Krylov space smaller than n_keep");
+    std::vector<double> Tm((size_t)m * m, 0.0);
+    for (int j = 0; j < done; ++j)
+        for (int a = 0; a < NB; ++a)
+            for (int c = 0; c < NB; ++c) Tm[(size_t)(j * NB + a) * m + j * NB + c] = As[j][a * NB + c];
+    for (int j = 0; j + 1 < done; ++j)
+        for (int a = 0; a < NB; ++a)
+            for (int c = 0; c < NB; ++c) {
+                Tm[(size_t)((j + 1) * NB + a) * m + j * NB + c] = Bs[j][a * NB + c];
+                Tm[(size_t)(j * NB + c) * m + (j + 1) * NB + a] = Bs[j][a * NB + c];
+            }
+    std::vector<double> theta, Zm;
+    sym_eig(m, Tm, theta, Zm);
+    const int nk = o->n_keep;
+    std::vector<double> S((size_t)m * nk);
+    for (int l = 0; l < m; ++l)
+        for (int c = 0; c < nk; ++c) S[(size_t)l * nk + c] = Zm[(size_t)l * m + c];
+    hip_check(hipMemcpyAsync(z.Sd, S.data(), S.size() * 8, hipMemcpyHostToDevice, st), "coefficient copy");
+    for (int c0 = 0; c0 < nk; c0 += 16) {
+        const int nc = std::min(16, nk - c0);
+        hipLaunchKernelGGL((k_britz<T, NB>), dim3((int)((dim + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                           (const T *)b.blk(0), b.ldb, done, (const double *)z.Sd, nk, c0, nc, z.ritz + c0 * dim,
+                           dim);
+    }
+    hip_check(hipGetLastError(), "ritz launch");
+    z.finish_ritz(theta, nk, o->refine != 0, evals, resid);
+    if (n_done) *n_done = done;
+}
+
+template <typename T>
+void run_block_nb(const fotci_ham *h, const fotci_block_lanczos_opts *o, const double *pivot, char *work,
+                  double *evals, double *resid, double *evecs, int32_t *n_done, hipStream_t st) {
+    switch (o->n_block) {
+        case 1: run_block<T, 1>(h, o, pivot, work, evals, resid, evecs, n_done, st); break;
+        case 2: run_block<T, 2>(h, o, pivot, work, evals, resid, evecs, n_done, st); break;
+        case 4: run_block<T, 4>(h, o, pivot, work, evals, resid, evecs, n_done, st); break;
+        default: run_block<T, 8>(h, o, pivot, work, evals, resid, evecs, n_done, st); break;
+    }
+}
+
 }  // namespace
 
 int64_t lanczos_bytes(const fotci_ham *h, const fotci_lanczos_opts *o) { return standard_layout(h, o).total; }
@@ -707,6 +1206,35 @@ void trlan_run(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivo
         run_trlan<float>(h, o, pivot, (char *)work, evals, resid, evecs, stats, st);
     else
         run_trlan<double>(h, o, pivot, (char *)work, evals, resid, evecs, stats, st);
+}
+
+void check_block_opts(const fotci_block_lanczos_opts *o) {
+    if (o->n_keep < 1 || o->n_keep > 16) fail(FOTCI_EINVAL, "n_keep must be in 1..16");
+    if (o->n_block != 1 && o->n_block != 2 && o->n_block != 4 && o->n_block != 8)
+        fail(FOTCI_EINVAL, "n_block must be 1, 2, 4 or 8");
+    if (o->n_iter < 1 || (int64_t)o->n_iter * o->n_block > kMaxIter)
+        fail(FOTCI_EINVAL, "n_iter must be >= 1 with n_iter * n_block <= 4096");
+    if (o->mode != FOTCI_MODE_F64 && o->mode != FOTCI_MODE_F32)
+        fail(FOTCI_EINVAL, "block Lanczos needs FOTCI_MODE_F64 or FOTCI_MODE_F32");
+}
+
+int64_t block_lanczos_bytes(const fotci_ham *h, const fotci_block_lanczos_opts *o) {
+    check_block_opts(o);
+    return block_layout(h, o).total;
+}
+
+void block_lanczos_run(const fotci_ham *h, const fotci_block_lanczos_opts *o, const double *pivot, void *work,
+                       int64_t work_bytes, double *evals, double *resid, double *evecs, int32_t *n_done,
+                       void *stream) {
+    check_block_opts(o);
+    if (work_bytes < block_lanczos_bytes(h, o)) fail(FOTCI_ENOMEM, "Lanczos workspace too small");
+    if (((uintptr_t)work & 255u) != 0) fail(FOTCI_EINVAL, "workspace must be 256-byte aligned");
+    if (((uintptr_t)pivot & 15u) != 0) fail(FOTCI_EINVAL, "pivot block must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    if (o->mode == FOTCI_MODE_F32)
+        run_block_nb<float>(h, o, pivot, (char *)work, evals, resid, evecs, n_done, st);
+    else
+        run_block_nb<double>(h, o, pivot, (char *)work, evals, resid, evecs, n_done, st);
 }
 
 }  // namespace fotci

@@ -1,0 +1,158 @@
+// Device helpers shared by the tiled apply_H kernels (one vector, and blocks
+// of vectors stored element-major): tile sizes, matrix-core wrappers, buffer
+// loads, the per-wave R tile layout of the pn contraction and the gather-list
+// bookkeeping. Included by the .hip files only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fotci_internal.h"
+
+namespace fotci {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;      // threads per workgroup (4 waves)
+constexpr int kTile = 8;     // rows (nn kernel) / columns (pp kernel) per tile
+constexpr int kLdsTile = 131072;  // bytes of LDS for a staged tile (gfx950: up to 160 KiB per workgroup)
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<float> {
+    typedef floatx4 acc_t;
+    static __device__ __forceinline__ acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // output row of accumulator element r held by `lane` (column = lane % 16)
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct Mma<double> {
+    typedef doublex4 acc_t;
+    static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // the float64 variant interleaves rows: element r of `lane` is row lane/16 + 4r
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <typename T>
+struct TabT;
+template <>
+struct TabT<double> {
+    static __device__ __forceinline__ const double *diag(const DevSpecies &s) { return s.d64; }
+    static __device__ __forceinline__ const double *vq(const DevHam &h) { return h.vq64; }
+    static __device__ __forceinline__ const double *nn_ell(const DevTiled &t) { return t.nn_ell_v64; }
+    static __device__ __forceinline__ const double *pp_ell(const DevTiled &t) { return t.pp_ell_v64; }
+};
+template <>
+struct TabT<float> {
+    static __device__ __forceinline__ const float *diag(const DevSpecies &s) { return s.d32; }
+    static __device__ __forceinline__ const float *vq(const DevHam &h) { return h.vq32; }
+    static __device__ __forceinline__ const float *nn_ell(const DevTiled &t) { return t.nn_ell_v32; }
+    static __device__ __forceinline__ const float *pp_ell(const DevTiled &t) { return t.pp_ell_v32; }
+};
+
+constexpr int kPnThreads = 64 * kPnWaves;
+constexpr int kPnHalves = kPnTile / 16;   // 16-column matrix-core blocks per tile
+constexpr unsigned kBufFlags = 0x00020000u;   // raw buffer, 32-bit data format
+constexpr unsigned kOutOfRange = 0x7ff00000u;  // byte offset beyond any x
+
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+// flip the sign of v when bit 31 of code is set
+__device__ __forceinline__ float signed_by(float v, uint32_t code) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ (code & 0x80000000u));
+}
+__device__ __forceinline__ double signed_by(double v, uint32_t code) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)(code & 0x80000000u) << 32));
+}
+
+
+// LDS layout of the per-wave tile R[B][col] (B < 64 neutron labels, col <
+// kPnTile source columns): column-major with column stride kPnRStride = 68
+// elements. float: a lane's four accumulator rows (4 consecutive B) leave in
+// one 16-byte store, and 8 lanes of a store cover all 32 banks. double: the
+// accumulator rows of a lane are 4 apart and leave in four stores. h selects
+// the 16-column block of the tile.
+template <typename T>
+struct Lds;
+template <>
+struct Lds<float> {
+    static __device__ __forceinline__ void store(float *R, int lane, int h, int bt, const floatx4 &acc) {
+        *(floatx4 *)(R + ((lane & 15) + 16 * h) * kPnRStride + 16 * bt + 4 * (lane >> 4)) = acc;
+    }
+};
+template <>
+struct Lds<double> {
+    static __device__ __forceinline__ void store(double *R, int lane, int h, int bt, const doublex4 &acc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            R[((lane & 15) + 16 * h) * kPnRStride + 16 * bt + Mma<double>::row(lane, r)] = acc[r];
+    }
+};
+
+__device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0);
+}
+
+constexpr int kPnRounds = 8;   // gather rounds of a tile loaded with the tile's x values
+
+// One gather entry: yl[dst] += phase * R[element] (code layout as in
+// pn_code). With private rows the padding code is applied too (it adds to
+// the padding column); with the shared row it is skipped.
+template <typename T, bool PRIV>
+__device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__ R, uint32_t c, uint32_t null_code) {
+    const T v = signed_by(R[c & ((1u << kPnRBits) - 1u)], c);
+    const uint32_t d = (c >> kPnRBits) & ((1u << kPnDstBits) - 1u);
+    if (PRIV)
+        yl[d] += v;
+    else if (c != null_code)
+        atomicAdd(&yl[d], v);
+}
+
+// Gather-list ranges of the wave's tiles t = wid + W*(j0 + lane), one tile
+// per lane (ends past the last tile clamp to it), read once per 64 tiles so
+// that the tile loop picks them with readlane and issues no dependent load.
+struct PnBounds {
+    int b0, b1;
+};
+
+__device__ __forceinline__ void pn_bounds(PnBounds &pb, int j0, int wid, int ntiles, const int32_t *__restrict__ pnp,
+                                          int lane) {
+    const int tt = wid + kPnWaves * (j0 + lane);
+    pb.b0 = pnp[min(tt, ntiles)];
+    pb.b1 = pnp[min(tt + 1, ntiles)];
+}
+
+// Operands of one operator class for a destination row.
+struct PnClass {
+    const int32_t *ob_code;   // proton one-body jumps into the row for this class: (local op << 1) | sign
+    const int64_t *ob_base;   // their source rows' offsets in x
+    int a0, kp, nB;
+    uint32_t null_code;       // padding entry of the gather lists
+};
+
+// Largest tile (8, 4, 2 or 1 rows or columns) whose staged slab of max_len
+// elements of elem bytes each fits kLdsTile.
+inline int pick_tile(int max_len, int elem) {
+    int t = kTile;
+    while (t > 1 && (int64_t)t * max_len * elem > kLdsTile) t >>= 1;
+    return t;
+}
+
+}  // namespace
+}  // namespace fotci

@@ -32,7 +32,7 @@ EXPORTED = [
     "fotci_lanczos_lowest", "fotci_trlan_workspace_bytes", "fotci_lanczos_thick_restart",
     "fotci_ham_op_counts", "fotci_ham_pn_work", "fotci_ham_set_pn_private_rows",
     "fotci_tridiag_eigh", "fotci_sym_eigh", "fotci_decouple_tbme", "fotci_profile_start",
-    "fotci_profile_stop",
+    "fotci_profile_stop", "fotci_apply_H_block", "fotci_block_lanczos_workspace_bytes", "fotci_lanczos_block",
 ]
 
 
@@ -56,6 +56,11 @@ class TrlanOpts(ctypes.Structure):
     _fields_ = [("n_keep", ctypes.c_int32), ("n_thick", ctypes.c_int32), ("n_basis", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("mode", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("reorth", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class BlockLanczosOpts(ctypes.Structure):
+    _fields_ = [("n_keep", ctypes.c_int32), ("n_block", ctypes.c_int32), ("n_iter", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("refine", ctypes.c_int32)]
 
 
 _lib = None
@@ -101,6 +106,9 @@ def lib():
         "fotci_decouple_tbme": (ctypes.c_int, [I32, P, P, I32, P, I32, P, I32, P, P, P, P]),
         "fotci_profile_start": (ctypes.c_int, [P, I32]),
         "fotci_profile_stop": (ctypes.c_int, [P, P, P, P, P]),
+        "fotci_apply_H_block": (ctypes.c_int, [P, I32, I32, P, P, P]),
+        "fotci_block_lanczos_workspace_bytes": (I64, [P, P]),
+        "fotci_lanczos_block": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(l, name)
@@ -266,6 +274,18 @@ class Hamiltonian:
         _check(lib().fotci_apply_H(self._h, m, _dev_ptr(x), _dev_ptr(y), _stream(stream)))
         return y
 
+    def apply_block(self, x, y=None, mode="f64", stream=None):
+        """Y = H X for a block X of shape (dim, n_block), row-major (vector index fastest)."""
+        import torch
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        dt = torch.float64 if m in (MODE_F64, MODE_F64_PLAIN) else torch.float32
+        if (x.dtype != dt or not x.is_cuda or not x.is_contiguous() or x.dim() != 2 or x.shape[0] != self.dim):
+            raise ValueError("x must be a contiguous %s device tensor of shape (%d, n_block)" % (dt, self.dim))
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().fotci_apply_H_block(self._h, m, int(x.shape[1]), _dev_ptr(x), _dev_ptr(y), _stream(stream)))
+        return y
+
     def vjp(self, x, g, want_dx=True, stream=None):
         """(dx, grads) of L = <g, H x>: dx = H g and label-wise densities."""
         import torch
@@ -323,6 +343,39 @@ class Hamiltonian:
                                           _np_ptr(resid), _dev_ptr(evecs), _np_ptr(alpha), _np_ptr(beta),
                                           _stream(stream)))
         out = dict(evals=evals, resid=resid, alpha=alpha, beta=beta)
+        if want_vectors:
+            out["evecs"] = evecs
+        return out
+
+    def block_lanczos_workspace_bytes(self, n_keep, n_block, n_iter, mode="f64", refine=True):
+        o = BlockLanczosOpts(n_keep, n_block, n_iter, MODES[mode] if isinstance(mode, str) else int(mode),
+                             int(refine))
+        n = lib().fotci_block_lanczos_workspace_bytes(self._h, ctypes.byref(o))
+        if n < 0:
+            _check(int(n))
+        return int(n)
+
+    def lanczos_block(self, pivot, n_keep, n_iter, mode="f64", refine=True, want_vectors=False, work=None,
+                      stream=None):
+        """Block Lanczos from a pivot block (dim, n_block) float64; returns dict(evals, resid, n_done[, evecs])."""
+        import torch
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        if (pivot.dtype != torch.float64 or pivot.dim() != 2 or pivot.shape[0] != self.dim
+                or not pivot.is_contiguous()):
+            raise ValueError("pivot must be a contiguous float64 device tensor of shape (dim, n_block)")
+        nb = int(pivot.shape[1])
+        o = BlockLanczosOpts(n_keep, nb, n_iter, m, int(refine))
+        nbytes = self.block_lanczos_workspace_bytes(n_keep, nb, n_iter, m, refine)
+        if work is None or work.numel() < nbytes + 256:
+            work = torch.empty(nbytes + 256, dtype=torch.uint8, device=pivot.device)
+        wptr = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        evals = np.zeros(n_keep)
+        resid = np.zeros(n_keep)
+        done = np.zeros(1, dtype=np.int32)
+        evecs = torch.empty(n_keep, self.dim, dtype=torch.float64, device=pivot.device) if want_vectors else None
+        _check(lib().fotci_lanczos_block(self._h, ctypes.byref(o), _dev_ptr(pivot), wptr, nbytes, _np_ptr(evals),
+                                         _np_ptr(resid), _dev_ptr(evecs), _np_ptr(done), _stream(stream)))
+        out = dict(evals=evals, resid=resid, n_done=int(done[0]), workspace_bytes=int(nbytes))
         if want_vectors:
             out["evecs"] = evecs
         return out

@@ -308,3 +308,27 @@ def test_package_j_squared_elements_match_oracle():
         assert np.allclose(eps, direct["eps_p"], atol=0)
         for k in ("v_pp", "v_nn", "v_pn"):
             assert np.max(np.abs(lib[k] - direct[k])) < 1e-12, k
+
+
+def test_block_options_and_arguments_are_checked():
+    """Block Lanczos options and the block apply's arguments are validated on
+    the host before anything touches the device."""
+    import ctypes
+    w = inputs.WORKLOADS["sd_2p2n"]
+    inter, _ = inputs.random_interaction(w["two_j"], 3)
+    h = fotci.Hamiltonian.build(w["two_j"], w["Z"], w["N"], w["two_M"], inter, upload=False)
+    good = h.block_lanczos_workspace_bytes(5, 4, 40, "f32")
+    assert good > h.block_lanczos_workspace_bytes(5, 4, 20, "f32") > 0
+    assert h.block_lanczos_workspace_bytes(5, 4, 40, "f64") > good
+    for bad in [dict(n_keep=0, n_block=4, n_iter=10), dict(n_keep=17, n_block=4, n_iter=10),
+                dict(n_keep=5, n_block=3, n_iter=10), dict(n_keep=5, n_block=4, n_iter=0),
+                dict(n_keep=5, n_block=8, n_iter=513), dict(n_keep=5, n_block=4, n_iter=10, mode="f64_plain")]:
+        with pytest.raises(fotci.FotciError) as ei:
+            h.block_lanczos_workspace_bytes(**bad)
+        assert ei.value.code == -1   # FOTCI_EINVAL
+    fake = ctypes.c_void_p(1 << 20)
+    apply_block = fotci.lib().fotci_apply_H_block
+    for mode, nb, code in [(fotci.MODE_F64, 3, -1), (fotci.MODE_F64_PLAIN, 2, -1), (7, 2, -1),
+                           (fotci.MODE_F64, 4, -5), (fotci.MODE_F64_PLAIN, 1, -5)]:
+        rc = apply_block(h._h, mode, nb, fake, ctypes.c_void_p((1 << 20) + (1 << 24)), None)
+        assert rc == code, (mode, nb, rc)
