@@ -142,8 +142,8 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
 // tile on the matrix cores (16 columns per instruction) into a wave-private
 // R in LDS and gathers the neutron jumps whose source lies in the tile into
 // its output row. x is read with buffer loads: each lane's offset is fixed
-// for the whole class and the tile offset is scalar; padding lanes point past
-// the end of x and read zero.
+// for the whole class and the tile's column offset is added to it; padding
+// lanes point past the end of x and read zero.
 
 // The loads of one source tile: KST x values per lane for each 16-column
 // block and the first kPnRounds rounds of gather codes. Their number is fixed
@@ -167,12 +167,14 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
     const int tc = min(tt, ntiles - 1);
     b.e0 = __builtin_amdgcn_readlane(pb.b0, j & 63);
     b.e1 = tt < ntiles ? __builtin_amdgcn_readlane(pb.b1, j & 63) : b.e0;
-    const unsigned soff = (unsigned)(kPnTile * tc) * (unsigned)sizeof(T);
+    // the whole offset goes into the range-checked vector offset, so the
+    // ragged last tile of the last row reads zero past the end of x
+    const unsigned toff = (unsigned)(kPnTile * tc) * (unsigned)sizeof(T);
 #pragma unroll
     for (int h = 0; h < kPnHalves; ++h)
 #pragma unroll
         for (int ks = 0; ks < KST; ++ks)
-            b.xv[h][ks] = buffer_load<T>(xr, voff[ks], soff + (unsigned)(16 * h * sizeof(T)));
+            b.xv[h][ks] = buffer_load<T>(xr, voff[ks] + toff + (unsigned)(16 * h * sizeof(T)), 0);
 #pragma unroll
     for (int i = 0; i < kPnRounds; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
 }
