@@ -66,9 +66,12 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
         const int nr = min(RT, rend - r0);
         const RowT *xs = xb + off + (int64_t)r0 * nn;
         __syncthreads();
+#pragma unroll 4
         for (int idx = tid; idx < RT * nn; idx += kT) {
             const int r = idx / nn, c = idx - r * nn;
-            Xl[c * RT + r] = r < nr ? xs[(int64_t)r * nn + c] : row_zero<T, NB>();
+            // rows past the tile's end load row nr-1 and store zero: no branch around the load
+            const RowT v = xs[(int64_t)min(r, nr - 1) * nn + c];
+            Xl[c * RT + r] = r < nr ? v : row_zero<T, NB>();
         }
         T dp[RT];
 #pragma unroll
@@ -83,6 +86,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
 #pragma unroll
                 for (int v = 0; v < NB; ++v) acc[r][v] = (dp[r] + dnc) * xr.v[v];
             }
+#pragma unroll 4
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * nn + c;
                 const int src = TT.nn_ell_src[k];
@@ -127,9 +131,11 @@ __global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *_
     for (int c0 = c0t; c0 < cend; c0 += CT) {
         const int nc = min(CT, cend - c0);
         __syncthreads();
+#pragma unroll 4
         for (int idx = tid; idx < np * CT; idx += kT) {
             const int r = idx / CT, c = idx - r * CT;
-            Xl[idx] = c < nc ? xb[off + (int64_t)r * nn + c0 + c] : row_zero<T, NB>();
+            const RowT v = xb[off + (int64_t)r * nn + c0 + min(c, nc - 1)];   // unconditional load
+            Xl[idx] = c < nc ? v : row_zero<T, NB>();
         }
         __syncthreads();
         for (int r = tid; r < np; r += kT) {
@@ -138,6 +144,7 @@ __global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *_
             for (int c = 0; c < CT; ++c)
 #pragma unroll
                 for (int v = 0; v < NB; ++v) acc[c][v] = 0;
+#pragma unroll 4
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * np + r;
                 const int src = TT.pp_ell_src[k];

@@ -66,9 +66,12 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
         const int nr = min(RT, rend - r0);
         const T *xs = x + off + (int64_t)r0 * nn;
         __syncthreads();
+#pragma unroll 4
         for (int idx = tid; idx < RT * nn; idx += kT) {
             const int r = idx / nn, c = idx - r * nn;
-            Xl[c * RT + r] = r < nr ? xs[(int64_t)r * nn + c] : T(0);
+            // rows past the tile's end load row nr-1 and store zero: no branch around the load
+            const T v = xs[(int64_t)min(r, nr - 1) * nn + c];
+            Xl[c * RT + r] = r < nr ? v : T(0);
         }
         T dp[RT];
 #pragma unroll
@@ -79,6 +82,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
             const T dnc = dn[nf + c];
 #pragma unroll
             for (int r = 0; r < RT; ++r) acc[r] = (dp[r] + dnc) * Xl[c * RT + r];
+#pragma unroll 4
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * nn + c;
                 const int src = TT.nn_ell_src[k];
@@ -112,15 +116,18 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
     for (int c0 = c0t; c0 < cend; c0 += CT) {
         const int nc = min(CT, cend - c0);
         __syncthreads();
+#pragma unroll 4
         for (int idx = tid; idx < np * CT; idx += kT) {
             const int r = idx / CT, c = idx - r * CT;
-            Xl[idx] = c < nc ? x[off + (int64_t)r * nn + c0 + c] : T(0);
+            const T v = x[off + (int64_t)r * nn + c0 + min(c, nc - 1)];   // unconditional load
+            Xl[idx] = c < nc ? v : T(0);
         }
         __syncthreads();
         for (int r = tid; r < np; r += kT) {
             T acc[CT];
 #pragma unroll
             for (int c = 0; c < CT; ++c) acc[c] = 0;
+#pragma unroll 4
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * np + r;
                 const int src = TT.pp_ell_src[k];
