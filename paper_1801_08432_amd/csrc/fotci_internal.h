@@ -252,6 +252,8 @@ void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void
                         void **events = nullptr);
 void launch_apply_block(const DevHam &d, const DevTiled &t, int mode, int nb, const void *x, void *y, void *stream,
                         void **events = nullptr);
+// pn part of the block apply (nb 2, 4 or 8; adds to y): the one-vector pn kernel with a vector stride
+void launch_pn_block(const DevHam &d, const DevTiled &t, int mode, int nb, const void *x, void *y, void *stream);
 // block apply with the per-kernel timing of launch_apply; nb == 1 is launch_apply
 void launch_apply_nb(const fotci_ham *h, int mode, int nb, const void *x, void *y, void *stream);
 void build_tiled_tables(fotci_ham *h);

@@ -199,7 +199,7 @@ void launch_apply_nb(const fotci_ham *h, int mode, int nb, const void *x, void *
         pr.n_kernels = 3;
         pr.names[0] = "k_nn_diag_blk";
         pr.names[1] = "k_pp_blk";
-        pr.names[2] = "k_pn_blk";
+        pr.names[2] = "k_pn";
         pr.calls++;
     }
 }

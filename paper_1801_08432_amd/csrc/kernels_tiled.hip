@@ -165,9 +165,9 @@ struct PnTile {
 
 // Tile j of the wave (t = wid + W*j); past the last tile it reloads that tile
 // and is marked empty.
-template <typename T, int KST>
+template <typename T, int KST, int NB>
 __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int ntiles, PnBounds &pb,
-                                         const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+                                         const unsigned *voff, unsigned goff, __amdgpu_buffer_rsrc_t xr,
                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int lane) {
     if (j > 0 && (j & 63) == 0) pn_bounds(pb, j, wid, ntiles, pnp, lane);   // uniform, every 64 tiles
     const int tt = wid + kPnWaves * j;
@@ -176,12 +176,12 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
     b.e1 = tt < ntiles ? __builtin_amdgcn_readlane(pb.b1, j & 63) : b.e0;
     // the whole offset goes into the range-checked vector offset, so the
     // ragged last tile of the last row reads zero past the end of x
-    const unsigned toff = (unsigned)(kPnTile * tc) * (unsigned)sizeof(T);
+    const unsigned toff = (unsigned)(kPnTile * tc) * (unsigned)(NB * sizeof(T)) + goff;
 #pragma unroll
     for (int h = 0; h < kPnHalves; ++h)
 #pragma unroll
         for (int ks = 0; ks < KST; ++ks)
-            b.xv[h][ks] = buffer_load<T>(xr, voff[ks] + toff + (unsigned)(16 * h * sizeof(T)), 0);
+            b.xv[h][ks] = buffer_load<T>(xr, voff[ks] + toff + (unsigned)(16 * h * NB * sizeof(T)), 0);
 #pragma unroll
     for (int i = 0; i < kPnRounds; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
 }
@@ -236,8 +236,9 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
 // tables: lane (col_l, kq) holds C[B = 16 bt + col_l][k = 4 ks + kq] =
 // phase_k V^q[A_k, B] for the matrix cores and the byte offset of its x
 // element in source row k; no workgroup barrier separates the classes.
-template <typename T, bool PRIV, int NBT, int KST>
-__device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict__ V, __amdgpu_buffer_rsrc_t xr,
+template <typename T, bool PRIV, int NBT, int KST, int NB>
+__device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict__ V, unsigned goff,
+                                         __amdgpu_buffer_rsrc_t xr,
                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
                                          int wid, int lane, T *__restrict__ R, T *__restrict__ yl) {
     if (wid >= ntiles) return;
@@ -249,7 +250,7 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
         const int k = 4 * ks + kq;
         const bool ok = k < pc.kp;
         const int code = ok ? pc.ob_code[pc.a0 + k] : 0;
-        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)sizeof(T) : kOutOfRange;
+        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)(NB * sizeof(T)) : kOutOfRange;
 #pragma unroll
         for (int bt = 0; bt < NBT; ++bt) {
             const int B = 16 * bt + col_l;
@@ -263,61 +264,75 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
     if constexpr (sizeof(T) == 4) {
         // three register sets in rotation: tiles j+1 and j+2 are in flight while tile j is worked on
         PnTile<T, KST> A, B, C;
-        pn_fetch<T, KST>(A, 0, wid, ntiles, pb, voff, xr, pnp, cres, lane);
-        pn_fetch<T, KST>(B, 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_fetch<T, KST, NB>(A, 0, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
+        pn_fetch<T, KST, NB>(B, 1, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
         for (int j = 0;; j += 3) {
-            pn_fetch<T, KST>(C, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_fetch<T, KST, NB>(C, j + 2, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
             pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
             if (wid + W * (j + 1) >= ntiles) break;
-            pn_fetch<T, KST>(A, j + 3, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_fetch<T, KST, NB>(A, j + 3, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
             pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
             if (wid + W * (j + 2) >= ntiles) break;
-            pn_fetch<T, KST>(B, j + 4, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_fetch<T, KST, NB>(B, j + 4, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
             pn_work<T, PRIV, NBT, KST>(C, cv, cres, pc.null_code, lane, R, yl);
             if (wid + W * (j + 3) >= ntiles) break;
         }
     } else {
         // double: two register sets (the operands are twice as wide)
         PnTile<T, KST> A, B;
-        pn_fetch<T, KST>(A, 0, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+        pn_fetch<T, KST, NB>(A, 0, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
         for (int j = 0;; j += 2) {
-            pn_fetch<T, KST>(B, j + 1, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_fetch<T, KST, NB>(B, j + 1, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
             pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
             if (wid + W * (j + 1) >= ntiles) break;
-            pn_fetch<T, KST>(A, j + 2, wid, ntiles, pb, voff, xr, pnp, cres, lane);
+            pn_fetch<T, KST, NB>(A, j + 2, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
             pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
             if (wid + W * (j + 2) >= ntiles) break;
         }
     }
 }
 
-template <typename T, bool PRIV, int NBT>
-__device__ __forceinline__ void pn_tiles_k(int ksteps, const PnClass &pc, const T *V, __amdgpu_buffer_rsrc_t xr,
+template <typename T, bool PRIV, int NBT, int NB>
+__device__ __forceinline__ void pn_tiles_k(int ksteps, const PnClass &pc, const T *V, unsigned goff,
+                                           __amdgpu_buffer_rsrc_t xr,
                                            const int32_t *pnp, __amdgpu_buffer_rsrc_t pnc, int ntiles, int wid,
                                            int lane, T *R, T *yl) {
     switch (ksteps) {
-        case 1: pn_tiles<T, PRIV, NBT, 1>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 2: pn_tiles<T, PRIV, NBT, 2>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 3: pn_tiles<T, PRIV, NBT, 3>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 4: pn_tiles<T, PRIV, NBT, 4>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 5: pn_tiles<T, PRIV, NBT, 5>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 6: pn_tiles<T, PRIV, NBT, 6>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 7: pn_tiles<T, PRIV, NBT, 7>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        default: pn_tiles<T, PRIV, NBT, 8>(pc, V, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 1: pn_tiles<T, PRIV, NBT, 1, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 2: pn_tiles<T, PRIV, NBT, 2, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 3: pn_tiles<T, PRIV, NBT, 3, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 4: pn_tiles<T, PRIV, NBT, 4, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 5: pn_tiles<T, PRIV, NBT, 5, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 6: pn_tiles<T, PRIV, NBT, 6, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 7: pn_tiles<T, PRIV, NBT, 7, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        default: pn_tiles<T, PRIV, NBT, 8, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
     }
 }
 
 // PRIV: each wave accumulates into its own output row (kPnWaves rows of
 // max_nn + 1 in dynamic LDS, summed at the end); otherwise one shared row
-// with atomics.
-template <typename T, bool PRIV>
+// with atomics. NB: x and y hold a block of NB vectors stored row-wise
+// (element i of vector v at i * NB + v) and a workgroup handles one vector
+// g0 of one destination row; NB == 1 is the one-vector apply. For NB > 1 the
+// grid is 1-D and the NB workgroups of a row are consecutive slots of one XCD
+// (workgroups are dealt to the 8 XCDs in turn), so the strided loads of the
+// block's vectors share that XCD's L2.
+template <typename T, bool PRIV, int NB>
 __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const T *__restrict__ x,
                                                    T *__restrict__ y) {
     __shared__ __align__(16) T Rw[kPnWaves][kPnTile * kPnRStride];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *yall = reinterpret_cast<T *>(smem_raw);   // output row(s) [nn]
 
-    const int ip = TT.order[blockIdx.x];
+    int slot = blockIdx.x, g0 = 0;
+    if constexpr (NB > 1) {
+        const int xcd = blockIdx.x & 7, s8 = blockIdx.x >> 3;
+        slot = (s8 / NB) * 8 + xcd;
+        g0 = s8 % NB;
+        if (slot >= P.p.n_sd) return;   // uniform: the grid is padded to a multiple of 8 rows
+    }
+    const int ip = TT.order[slot];
+    const unsigned goff = (unsigned)g0 * (unsigned)sizeof(T);
     const int tid = threadIdx.x;
     // the wave index is uniform across the wave: keep it (and the tile loop) scalar
     const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
     const int ntl = TT.n_t16;
     const T *vq = TabT<T>::vq(P);
     const __amdgpu_buffer_rsrc_t xr =
-        __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)sizeof(T)), kBufFlags);
+        __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)(NB * sizeof(T))), kBufFlags);
     const __amdgpu_buffer_rsrc_t cres =
         __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn_code, (short)0, (int)(TT.n_pn_code * 4), kBufFlags);
     T *R = Rw[wid];
@@ -359,10 +374,10 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
         const int ntiles = (nns + kPnTile - 1) / kPnTile;
         const int32_t *pnp = TT.pn_ptr + pslot;
         switch (nbt) {
-            case 1: pn_tiles_k<T, PRIV, 1>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            case 2: pn_tiles_k<T, PRIV, 2>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            case 3: pn_tiles_k<T, PRIV, 3>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            default: pn_tiles_k<T, PRIV, 4>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 1: pn_tiles_k<T, PRIV, 1, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 2: pn_tiles_k<T, PRIV, 2, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 3: pn_tiles_k<T, PRIV, 3, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            default: pn_tiles_k<T, PRIV, 4, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
         }
     }
     if (!any) return;
@@ -372,8 +387,24 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
         if (PRIV)
 #pragma unroll
             for (int w = 1; w < kPnWaves; ++w) v += yall[w * ystride + c];
-        y[base + c] += v;
+        y[(base + c) * NB + g0] += v;
     }
+}
+
+// float: wave-private output rows (plain LDS adds) when they fit; LDS float
+// atomics are far slower than a read and a write
+template <typename T, int NB>
+void launch_pn_nb(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_t st) {
+    const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1) * sizeof(T);
+    const dim3 grid = NB == 1 ? dim3(d.p.n_sd) : dim3((unsigned)((d.p.n_sd + 7) / 8 * 8 * NB));
+    bool priv = false;
+    if constexpr (sizeof(T) == 4) {
+        priv = t.pn_priv && lds_priv <= 32768;
+        if (priv) hipLaunchKernelGGL((k_pn<T, true, NB>), grid, dim3(kPnThreads), lds_priv, st, d, t, x, y);
+    }
+    if (!priv)
+        hipLaunchKernelGGL((k_pn<T, false, NB>), grid, dim3(kPnThreads), (size_t)(t.max_nn + 1) * sizeof(T), st, d,
+                           t, x, y);
 }
 
 template <typename T>
@@ -397,17 +428,7 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
         default: hipLaunchKernelGGL((k_pp<T, 1>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
     }
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[2], st), "event");
-    // float: wave-private output rows (plain LDS adds) when they fit; LDS
-    // float atomics are far slower than a read and a write
-    const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1) * sizeof(T);
-    bool priv = false;
-    if constexpr (sizeof(T) == 4) {
-        priv = t.pn_priv && lds_priv <= 32768;
-        if (priv) hipLaunchKernelGGL((k_pn<T, true>), dim3(d.p.n_sd), dim3(kPnThreads), lds_priv, st, d, t, x, y);
-    }
-    if (!priv)
-        hipLaunchKernelGGL((k_pn<T, false>), dim3(d.p.n_sd), dim3(kPnThreads), (size_t)(t.max_nn + 1) * sizeof(T), st,
-                           d, t, x, y);
+    launch_pn_nb<T, 1>(d, t, x, y, st);
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[3], st), "event");
 }
 
@@ -422,6 +443,27 @@ void launch_materialize_tiled(const DevHam &d, const DevTiled &t, void *stream) 
         hipLaunchKernelGGL(k_ell_values, dim3((unsigned)((t.pp_ell_len + kT - 1) / kT)), dim3(kT), 0, st,
                            t.pp_ell_ent, (const double *)d.p.off_val64, t.pp_ell_v64, t.pp_ell_v32, t.pp_ell_len);
     hip_check(hipGetLastError(), "materialize launch");
+}
+
+void launch_pn_block(const DevHam &d, const DevTiled &t, int mode, int nb, const void *x, void *y, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (mode == FOTCI_MODE_F64) {
+        const double *xd = (const double *)x;
+        double *yd = (double *)y;
+        switch (nb) {
+            case 2: launch_pn_nb<double, 2>(d, t, xd, yd, st); break;
+            case 4: launch_pn_nb<double, 4>(d, t, xd, yd, st); break;
+            default: launch_pn_nb<double, 8>(d, t, xd, yd, st); break;
+        }
+    } else {
+        const float *xf = (const float *)x;
+        float *yf = (float *)y;
+        switch (nb) {
+            case 2: launch_pn_nb<float, 2>(d, t, xf, yf, st); break;
+            case 4: launch_pn_nb<float, 4>(d, t, xf, yf, st); break;
+            default: launch_pn_nb<float, 8>(d, t, xf, yf, st); break;
+        }
+    }
 }
 
 void launch_apply_tiled(const DevHam &d, const DevTiled &t, int mode, const void *x, void *y, void *stream,
