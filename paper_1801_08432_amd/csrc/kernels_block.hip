@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
 #pragma unroll
                 for (int v = 0; v < NB; ++v) acc[r][v] = (dp[r] + dnc) * xr.v[v];
             }
-#pragma unroll 4
+#pragma unroll 8
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * nn + c;
                 const int src = TT.nn_ell_src[k];
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *_
             for (int c = 0; c < CT; ++c)
 #pragma unroll
                 for (int v = 0; v < NB; ++v) acc[c][v] = 0;
-#pragma unroll 4
+#pragma unroll 8
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * np + r;
                 const int src = TT.pp_ell_src[k];

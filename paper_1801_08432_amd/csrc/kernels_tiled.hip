@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
             const T dnc = dn[nf + c];
 #pragma unroll
             for (int r = 0; r < RT; ++r) acc[r] = (dp[r] + dnc) * Xl[c * RT + r];
-#pragma unroll 4
+#pragma unroll 8
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * nn + c;
                 const int src = TT.nn_ell_src[k];
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
             T acc[CT];
 #pragma unroll
             for (int c = 0; c < CT; ++c) acc[c] = 0;
-#pragma unroll 4
+#pragma unroll 8
             for (int e = 0; e < E; ++e) {
                 const int64_t k = eb + (int64_t)e * np + r;
                 const int src = TT.pp_ell_src[k];
