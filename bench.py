@@ -195,7 +195,6 @@ def block_lanczos_leg(h, mode, n_block, n_iter, ref=None):
     Krylov vector, residuals, and the lowest eigenvalues against a reference
     run when given."""
     import torch
-    from paper_1801_08432_amd import inputs
     piv = torch.from_numpy(np.random.default_rng(1804).standard_normal((h.dim, n_block))).to("cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
