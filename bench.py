@@ -342,6 +342,7 @@ def main():
                               s_per_iter={m: round(res[m][1] / a.lanczos_iters, 5) for m in res},
                               max_rel_eig_err=float(rel.max()),
                               max_resid={m: float(res[m][0]["resid"].max()) for m in res},
+                              resid_f64_plain=[float("%.3g" % v) for v in res["f64_plain"][0]["resid"]],
                               speedup_vs_f64_plain=round(res["f64_plain"][1] / res[mode][1], 3),
                               f64_tiled_rel_err_vs_plain=float(np.max(np.abs(res["f64"][0]["evals"] - e64) /
                                                                        np.abs(e64))),
@@ -363,6 +364,13 @@ def main():
             ref = res["f64_plain"][0]["evals"]
             tr["lowest5_rel_diff_vs_standard_f64_plain"] = float(np.max(np.abs(r["evals"][:5] - ref[:5]) /
                                                                        np.abs(ref[:5])))
+        # the same run in float64: all ten states converged on both sides
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r64 = h.lanczos_thick_restart(piv, 10, 30, 80, max_restarts=60, mode="f64", tol=1e-8)
+        tr["f64_seconds"] = round(time.perf_counter() - t0, 2)
+        tr["f64_converged"] = r64["converged"]
+        tr["max_rel_eig_err_vs_f64"] = float(np.max(np.abs(r["evals"] - r64["evals"]) / np.abs(r64["evals"])))
         out["thick_restart"] = tr
         log("[bench] thick restart: %s" % tr)
     if not a.no_block:
