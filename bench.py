@@ -126,6 +126,31 @@ def jcoupled_leg(w, mode):
                                    converged=r["converged"]))
 
 
+def vjp_leg(h, reps=2):
+    """Time the adjoint of apply_H (float64): dx = H g and every label density
+    dL/dV (Ch. 5 "Two-body densities"), with per-part HIP events; the pn
+    densities do one multiply-add per pn operation."""
+    import torch
+    from paper_1801_08432_amd import inputs
+    dev = "cuda:0"
+    g = torch.from_numpy(inputs.random_vector(h.dim, 1805)).to(dev)
+    x = torch.from_numpy(inputs.random_vector(h.dim, 1806)).to(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    res = {}
+    for want_dx in (True, False):
+        h.vjp(x, g, want_dx=want_dx)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            h.vjp(x, g, want_dx=want_dx)
+        ev[1].record()
+        torch.cuda.synchronize()
+        res["with_dx" if want_dx else "densities_only"] = round(ev[0].elapsed_time(ev[1]) / reps, 3)
+    pn_ops = h.op_counts()["pn"]
+    return dict(ms=res["with_dx"], densities_ms=res["densities_only"], pn_ops=pn_ops,
+                pn_gops=round(pn_ops / (res["densities_only"] * 1e-3) / 1e9, 2))
+
+
 def density_leg(h, w, reps=5):
     """Time the one-body transition densities of two float64 vectors; the
     streamed bytes are the g and x rows (proton side) and columns (neutron
@@ -224,6 +249,7 @@ def main():
     ap.add_argument("--no-trlan", action="store_true")
     ap.add_argument("--no-jcoupled", action="store_true")
     ap.add_argument("--no-block", action="store_true")
+    ap.add_argument("--no-vjp", action="store_true")
     ap.add_argument("--block-iters", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -379,6 +405,9 @@ def main():
         out["block"]["lanczos"] = block_lanczos_leg(h, mode, 4, a.block_iters, ref)
     if not a.no_density:
         out["one_body_density"] = density_leg(h, w)
+    if not a.no_vjp:
+        out["vjp"] = vjp_leg(h)
+        log("[bench] vjp: %s" % out["vjp"])
     if not a.no_jcoupled:
         out["jcoupled"] = jcoupled_leg(w, mode)
     if not a.no_cpu:

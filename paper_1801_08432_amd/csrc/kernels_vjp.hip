@@ -15,13 +15,12 @@
 
 #include <algorithm>
 
-#include "fotci_internal.h"
+#include "tiled_common.h"
 
 namespace fotci {
 
 namespace {
 
-constexpr int kT = 256;
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -91,11 +90,13 @@ __global__ __launch_bounds__(kT) void k_vjp_proton(DevHam P, const double *__res
     }
 }
 
-// Neutron side, one block per destination neutron SD jn: column dots over the
-// proton rows of its basis sector.
+// Neutron side, one block per destination neutron SD jn: the diagonal (the
+// column sums of g o x) and, with with_off, the off-diagonal entries as column
+// dots over the proton rows of its basis sector (used when the tiled tables
+// are not available; k_vjp_nn_sddmm otherwise).
 __global__ __launch_bounds__(kT) void k_vjp_neutron(DevHam P, const double *__restrict__ x,
                                                     const double *__restrict__ g, const double *dcol_n,
-                                                    double *d_spe_n, double *d_v_nn) {
+                                                    double *d_spe_n, double *d_v_nn, int with_off) {
     __shared__ double lds[kT / 64];
     const int jn = blockIdx.x;
     const int s = P.n_bsector[jn];
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(kT) void k_vjp_neutron(DevHam P, const double *__re
                 atomicAdd(&d_v_nn[code >> 1], (code & 1) ? -dd : dd);
             }
     }
-    if (!d_v_nn) return;
+    if (!d_v_nn || !with_off) return;
     for (int k = P.n.off_rowptr[jn]; k < P.n.off_rowptr[jn + 1]; ++k) {
         const int cs = P.n_local[P.n.off_col[k]];
         double a = 0.0;
@@ -176,6 +177,225 @@ __global__ __launch_bounds__(kT) void k_vjp_pn(DevHam P, const double *__restric
         const int lb = P.cls_ops[P.cls_off[qn] + i % nb];
         const int a = la / ns, c = la % ns, b = lb / ns, d = lb % ns;
         atomicAdd(&d_v_pn[((int64_t)a * ns + b) * ns2 + (int64_t)c * ns + d], v);
+    }
+}
+
+// nn two-body densities as a sampled product: in a basis sector s the entry
+// connecting neutron column cs to cd needs D[cd, cs] = sum_r g[r, cd] x[r, cs]
+// over the sector's proton rows, i.e. D = G_s^T X_s (G_s, X_s the row-major
+// np_s x nn_s blocks) sampled on the pattern of the neutron two-body jumps;
+// d_v_nn[label] += phase D[cd, cs] for every jump of the entry. One wave per
+// 32 x 32 tile of D that holds an entry: the sum over rows runs on the matrix
+// cores (16x16x4 float64, A = G^T, B = X, both read as 16-element row
+// segments), the tile goes to LDS, and the wave samples it at the ELL entries
+// of its 32 destination columns.
+constexpr int kSd = 32;
+
+__global__ __launch_bounds__(64) void k_vjp_nn_sddmm(DevHam P, DevTiled TT, const double *__restrict__ x,
+                                                     const double *__restrict__ g, double *d_v_nn) {
+    __shared__ double Dt[kSd][kSd + 1];
+    int b = blockIdx.x, s = 0;
+    for (; s < P.n_sectors; ++s) {
+        const int nb = (P.sec_nn[s] + kSd - 1) / kSd;
+        if (b < nb * nb) break;
+        b -= nb * nb;
+    }
+    if (s >= P.n_sectors) return;   // uniform
+    const int np = P.sec_np[s], nn = P.sec_nn[s];
+    const int nbk = (nn + kSd - 1) / kSd;
+    const int cd0 = kSd * (b / nbk), cs0 = kSd * (b % nbk);
+    const int64_t off = P.sec_off[s];
+    const int E = TT.nn_ell_E[s];
+    const int64_t eb = TT.nn_ell_base[s];
+    const int lane = threadIdx.x;
+    // skip tiles that no entry samples
+    bool hit = false;
+    for (int i = lane; i < kSd * E; i += 64) {
+        const int cd = cd0 + (i & (kSd - 1));
+        if (cd >= nn) continue;
+        const int64_t k = eb + (int64_t)(i / kSd) * nn + cd;
+        if (TT.nn_ell_ent[k] >= 0 && TT.nn_ell_src[k] >= cs0 && TT.nn_ell_src[k] < cs0 + kSd) hit = true;
+    }
+    if (__ballot(hit) == 0) return;   // uniform
+    doublex4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = Mma<double>::zero();
+    // lane: row r0 + lane / 16 of each 4-row step, column 16 i + lane % 16 of the tile
+    const int cl = lane & 15;
+    for (int r0 = 0; r0 < np; r0 += 4) {
+        const int r = r0 + (lane >> 4);
+        const double *gr = g + off + (int64_t)r * nn;
+        const double *xr = x + off + (int64_t)r * nn;
+        double a[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int cd = cd0 + 16 * i + cl, cs = cs0 + 16 * i + cl;
+            a[i] = r < np && cd < nn ? gr[cd] : 0.0;
+            bv[i] = r < np && cs < nn ? xr[cs] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = Mma<double>::mma(a[i], bv[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Dt[16 * i + Mma<double>::row(lane, q)][16 * j + cl] = acc[i][j][q];
+    __syncthreads();
+    for (int i = lane; i < kSd * E; i += 64) {
+        const int c = i & (kSd - 1), cd = cd0 + c;
+        if (cd >= nn) continue;
+        const int64_t k = eb + (int64_t)(i / kSd) * nn + cd;
+        const int ent = TT.nn_ell_ent[k];
+        const int src = TT.nn_ell_src[k];
+        if (ent < 0 || src < cs0 || src >= cs0 + kSd) continue;
+        const double dv = Dt[c][src - cs0];
+        for (int j = P.n.off_j0[ent]; j < P.n.off_j1[ent]; ++j) {
+            const int code = P.n.code2[j];
+            atomicAdd(&d_v_nn[code >> 1], (code & 1) ? -dv : dv);
+        }
+    }
+}
+
+// pn densities on the matrix cores: the transpose of the pn part of apply_H.
+// For a destination row ip' and class q with proton jumps k (source rows
+// ip_k, labels A_k, phases) and the neutron jumps of the conjugate class
+// grouped by 32-column source tile t:
+//   dV^q[A_k, B] += phase_k sum_t sum_so x[ip_k, 32t + so] G_t[so, B],
+//   G_t[so, B] = phase_l g[ip', dst_l] for the neutron jump l with source
+//   column 32t + so and label B (at most one: the source and the label fix
+//   the destination), 0 otherwise.
+// A wave scatters G_t for its tiles into its LDS tile -- the layout of the
+// forward kernel's R tile, so the gather codes address it unchanged; padding
+// codes are skipped -- contracts it with the x rows on the matrix cores
+// (M = proton jumps, N = labels B, K = source columns), then clears the
+// entries it wrote. Each wave adds its sums to dV_pn with float64 atomics.
+constexpr int kVjpThreads = 64 * kPnWaves;
+
+template <int KB, int NBT>
+__device__ __forceinline__ void vjp_pn_class(const DevHam &P, const DevTiled &TT, int a0, int kp, int nB, int q,
+                                             int qn, const int32_t *__restrict__ pnp, int ntiles,
+                                             __amdgpu_buffer_rsrc_t xr, const double *__restrict__ gl,
+                                             double *__restrict__ Gt, int wid, int lane, double *d_v_pn) {
+    doublex4 acc[KB][NBT];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) acc[kb][bt] = Mma<double>::zero();
+    // A operand: lane holds x[ip_k, column] for k = 16 kb + lane % 16 and the
+    // column lane / 16 of each 4-column step; rows past kp read zero
+    unsigned voff[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int k = 16 * kb + (lane & 15);
+        voff[kb] = k < kp ? (unsigned)(TT.p_ob_base[a0 + k] + (lane >> 4)) * 8u : kOutOfRange;
+    }
+    const uint32_t null_code = TT.pn_null;
+    constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
+    for (int t = wid; t < ntiles; t += kPnWaves) {
+        const int e0 = pnp[t], e1 = pnp[t + 1];
+        if (e0 == e1) continue;   // uniform: no neutron jump leaves this tile
+        for (int i = e0 + lane; i < e1; i += 64) {
+            const uint32_t c = TT.pn_code[i];
+            if (c != null_code) Gt[c & kElem] = signed_by(gl[(c >> kPnRBits) & kDst], c);
+        }
+        double xa[KB][kPnTile / 4];
+        const unsigned toff = (unsigned)(kPnTile * t) * 8u;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int ks = 0; ks < kPnTile / 4; ++ks) xa[kb][ks] = buffer_load<double>(xr, voff[kb] + toff + 32u * ks, 0);
+        // a wave's LDS operations complete in issue order: the reads below see
+        // the scatter above, and the clearing below follows the reads
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int ks = 0; ks < kPnTile / 4; ++ks) {
+            const double *Gr = Gt + (4 * ks + (lane >> 4)) * kPnRStride + (lane & 15);
+#pragma unroll
+            for (int bt = 0; bt < NBT; ++bt) {
+                const double b = Gr[16 * bt];
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) acc[kb][bt] = Mma<double>::mma(xa[kb][ks], b, acc[kb][bt]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int i = e0 + lane; i < e1; i += 64) {
+            const uint32_t c = TT.pn_code[i];
+            if (c != null_code) Gt[c & kElem] = 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int ns = P.ns;
+    const int64_t ns2 = (int64_t)ns * ns;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 16 * kb + Mma<double>::row(lane, r), B = 16 * bt + (lane & 15);
+                if (k >= kp || B >= nB) continue;
+                const int ck = P.p.ob_code[a0 + k];
+                const double v = (ck & 1) ? -acc[kb][bt][r] : acc[kb][bt][r];
+                if (v == 0.0) continue;
+                const int la = P.cls_ops[P.cls_off[q] + (ck >> 1)];
+                const int lb = P.cls_ops[P.cls_off[qn] + B];
+                const int a = la / ns, c = la % ns, b = lb / ns, d = lb % ns;
+                atomicAdd(&d_v_pn[((int64_t)a * ns + b) * ns2 + (int64_t)c * ns + d], v);
+            }
+}
+
+template <int KB>
+__device__ __forceinline__ void vjp_pn_nbt(int nbt, const DevHam &P, const DevTiled &TT, int a0, int kp, int nB,
+                                           int q, int qn, const int32_t *pnp, int ntiles, __amdgpu_buffer_rsrc_t xr,
+                                           const double *gl, double *Gt, int wid, int lane, double *d_v_pn) {
+    switch (nbt) {
+        case 1: vjp_pn_class<KB, 1>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
+        case 2: vjp_pn_class<KB, 2>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
+        case 3: vjp_pn_class<KB, 3>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
+        default: vjp_pn_class<KB, 4>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
+    }
+}
+
+// One workgroup per destination proton row: the row of g is staged in LDS
+// once, then every operator class with proton jumps into the row.
+__global__ __launch_bounds__(kVjpThreads) void k_vjp_pn_mfma(DevHam P, DevTiled TT, const double *__restrict__ x,
+                                                             const double *__restrict__ g, double *d_v_pn) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int gstride = (TT.max_nn + 2) & ~1;                  // keeps the tiles 16-byte aligned
+    double *gl = reinterpret_cast<double *>(smem_raw);          // [max_nn] row of g
+    double *Gall = gl + gstride;                                // [waves][kPnTile * kPnRStride]
+    const int ip = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int s = P.p_sector[ip];
+    const int nn = P.sec_nn[s];
+    const int64_t base = P.p_pstart[ip];
+    for (int c = tid; c < nn; c += kVjpThreads) gl[c] = g[base + c];
+    for (int i = tid; i < kPnWaves * kPnTile * kPnRStride; i += kVjpThreads) Gall[i] = 0.0;
+    __syncthreads();
+    double *Gt = Gall + wid * kPnTile * kPnRStride;
+    const __amdgpu_buffer_rsrc_t xr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)sizeof(double)), kBufFlags);
+    const int nq = P.nq, ntl = TT.n_t16;
+    for (int q = 0; q < nq; ++q) {
+        const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q], a1 = P.p.ob_ptr[(int64_t)ip * nq + q + 1];
+        if (a0 == a1) continue;   // uniform across the workgroup
+        const int qn = P.conjq[q];
+        const int nB = P.vq_nb[q];
+        const int nns = P.sec_nn[P.p_sector[P.p.ob_src[a0]]];
+        const int ntiles = (nns + kPnTile - 1) / kPnTile;
+        const int32_t *pnp = TT.pn_ptr + ((int64_t)s * nq + qn) * ntl;
+        const int kp = a1 - a0, nbt = (nB + 15) >> 4;
+        if (kp > 16)
+            vjp_pn_nbt<2>(nbt, P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn);
+        else
+            vjp_pn_nbt<1>(nbt, P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn);
     }
 }
 
@@ -283,13 +503,26 @@ void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const doub
     }
     if (d_spe_p || d_v_pp || need_n)
         hipLaunchKernelGGL(k_vjp_proton, dim3(d.p.n_sd), dim3(kT), 0, st, d, x, g, d_spe_p, d_v_pp, dcol);
+    const DevTiled &tt = h->dev_tiled;
+    const bool sddmm = d_v_nn && tt.ok;
     if (need_n) hipLaunchKernelGGL(k_vjp_neutron, dim3(d.n.n_sd), dim3(kT), 0, st, d, x, g, (const double *)dcol,
-                                   d_spe_n, d_v_nn);
+                                   d_spe_n, d_v_nn, sddmm ? 0 : 1);
+    if (sddmm) {
+        int64_t tiles = 0;
+        for (int nn : h->tc.sec_nn) tiles += (int64_t)((nn + kSd - 1) / kSd) * ((nn + kSd - 1) / kSd);
+        if (tiles > 0) hipLaunchKernelGGL(k_vjp_nn_sddmm, dim3((unsigned)tiles), dim3(64), 0, st, d, tt, x, g, d_v_nn);
+    }
     if (d_v_pn) {
-        for (int q = 0; q < d.nq; ++q)
-            if ((int64_t)h->j->cls.ops[q].size() * h->vq_nb[q] > kMaxBins)
-                fail(FOTCI_EINVAL, "pn operator class too large for the adjoint kernel");
-        hipLaunchKernelGGL(k_vjp_pn, dim3(d.p.n_sd * d.nq), dim3(kT), 0, st, d, x, g, d_v_pn);
+        const DevTiled &t = tt;
+        const size_t lds = ((size_t)((t.max_nn + 2) & ~1) + (size_t)kPnWaves * kPnTile * kPnRStride) * sizeof(double);
+        if (t.ok && lds <= 65536) {
+            hipLaunchKernelGGL(k_vjp_pn_mfma, dim3(d.p.n_sd), dim3(kVjpThreads), lds, st, d, t, x, g, d_v_pn);
+        } else {
+            for (int q = 0; q < d.nq; ++q)
+                if ((int64_t)h->j->cls.ops[q].size() * h->vq_nb[q] > kMaxBins)
+                    fail(FOTCI_EINVAL, "pn operator class too large for the adjoint kernel");
+            hipLaunchKernelGGL(k_vjp_pn, dim3(d.p.n_sd * d.nq), dim3(kT), 0, st, d, x, g, d_v_pn);
+        }
     }
     hip_check(hipGetLastError(), "vjp launch");
 }
