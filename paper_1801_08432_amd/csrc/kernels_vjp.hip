@@ -277,11 +277,81 @@ __global__ __launch_bounds__(64) void k_vjp_nn_sddmm(DevHam P, DevTiled TT, cons
 // entries it wrote. Each wave adds its sums to dV_pn with float64 atomics.
 constexpr int kVjpThreads = 64 * kPnWaves;
 
+// The loads of one tile (its x operands and the first kPnRounds rounds of
+// gather codes), issued a tile ahead of its use as in the forward kernel.
+template <int KB>
+struct VjpTile {
+    double xa[KB][kPnTile / 4];
+    uint32_t cr[kPnRounds];
+    int e0, e1;
+};
+
+// Tile j of the wave (t = wid + W*j); past the last tile it is marked empty.
+template <int KB>
+__device__ __forceinline__ void vjp_fetch(VjpTile<KB> &b, int j, int wid, int ntiles, const int32_t *__restrict__ pnp,
+                                          const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+                                          __amdgpu_buffer_rsrc_t cres, int lane) {
+    const int t = wid + kPnWaves * j;
+    const int tc = min(t, ntiles - 1);
+    b.e0 = pnp[tc];
+    b.e1 = t < ntiles ? pnp[tc + 1] : b.e0;
+    const unsigned toff = (unsigned)(kPnTile * tc) * 8u;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int ks = 0; ks < kPnTile / 4; ++ks) b.xa[kb][ks] = buffer_load<double>(xr, voff[kb] + toff + 32u * ks, 0);
+#pragma unroll
+    for (int i = 0; i < kPnRounds; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
+}
+
+// Scatter G_t (value) or clear it (value == false) for the tile's codes;
+// rounds past the prefetched ones are loaded here.
+__device__ __forceinline__ void vjp_scatter(const uint32_t (&cr)[kPnRounds], int e0, int ne, bool value,
+                                            __amdgpu_buffer_rsrc_t cres, uint32_t null_code,
+                                            const double *__restrict__ gl, double *__restrict__ Gt, int lane) {
+    constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
+    auto one = [&](uint32_t c) {
+        if (c == null_code) return;
+        Gt[c & kElem] = value ? signed_by(gl[(c >> kPnRBits) & kDst], c) : 0.0;
+    };
+#pragma unroll
+    for (int i = 0; i < kPnRounds; ++i)
+        if (64 * i < ne) one(cr[i]);
+    for (int i = 64 * kPnRounds; i < ne; i += 64) one(buffer_load_u32(cres, (unsigned)(e0 + i + lane) * 4u));
+}
+
+template <int KB, int NBT>
+__device__ __forceinline__ void vjp_work(const VjpTile<KB> &b, doublex4 (&acc)[KB][NBT], __amdgpu_buffer_rsrc_t cres,
+                                         uint32_t null_code, const double *__restrict__ gl, double *__restrict__ Gt,
+                                         int lane) {
+    if (b.e0 == b.e1) return;   // uniform: no neutron jump leaves this tile
+    const int ne = b.e1 - b.e0;
+    vjp_scatter(b.cr, b.e0, ne, true, cres, null_code, gl, Gt, lane);
+    // a wave's LDS operations complete in issue order: the reads below see
+    // the scatter above, and the clearing below follows the reads
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int ks = 0; ks < kPnTile / 4; ++ks) {
+        const double *Gr = Gt + (4 * ks + (lane >> 4)) * kPnRStride + (lane & 15);
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) {
+            const double v = Gr[16 * bt];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) acc[kb][bt] = Mma<double>::mma(b.xa[kb][ks], v, acc[kb][bt]);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    vjp_scatter(b.cr, b.e0, ne, false, cres, null_code, gl, Gt, lane);
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int KB, int NBT>
 __device__ __forceinline__ void vjp_pn_class(const DevHam &P, const DevTiled &TT, int a0, int kp, int nB, int q,
                                              int qn, const int32_t *__restrict__ pnp, int ntiles,
-                                             __amdgpu_buffer_rsrc_t xr, const double *__restrict__ gl,
-                                             double *__restrict__ Gt, int wid, int lane, double *d_v_pn) {
+                                             __amdgpu_buffer_rsrc_t xr, __amdgpu_buffer_rsrc_t cres,
+                                             const double *__restrict__ gl, double *__restrict__ Gt, int wid,
+                                             int lane, double *d_v_pn) {
+    if (wid >= ntiles) return;
     doublex4 acc[KB][NBT];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
@@ -296,39 +366,15 @@ __device__ __forceinline__ void vjp_pn_class(const DevHam &P, const DevTiled &TT
         voff[kb] = k < kp ? (unsigned)(TT.p_ob_base[a0 + k] + (lane >> 4)) * 8u : kOutOfRange;
     }
     const uint32_t null_code = TT.pn_null;
-    constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
-    for (int t = wid; t < ntiles; t += kPnWaves) {
-        const int e0 = pnp[t], e1 = pnp[t + 1];
-        if (e0 == e1) continue;   // uniform: no neutron jump leaves this tile
-        for (int i = e0 + lane; i < e1; i += 64) {
-            const uint32_t c = TT.pn_code[i];
-            if (c != null_code) Gt[c & kElem] = signed_by(gl[(c >> kPnRBits) & kDst], c);
-        }
-        double xa[KB][kPnTile / 4];
-        const unsigned toff = (unsigned)(kPnTile * t) * 8u;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-            for (int ks = 0; ks < kPnTile / 4; ++ks) xa[kb][ks] = buffer_load<double>(xr, voff[kb] + toff + 32u * ks, 0);
-        // a wave's LDS operations complete in issue order: the reads below see
-        // the scatter above, and the clearing below follows the reads
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int ks = 0; ks < kPnTile / 4; ++ks) {
-            const double *Gr = Gt + (4 * ks + (lane >> 4)) * kPnRStride + (lane & 15);
-#pragma unroll
-            for (int bt = 0; bt < NBT; ++bt) {
-                const double b = Gr[16 * bt];
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb) acc[kb][bt] = Mma<double>::mma(xa[kb][ks], b, acc[kb][bt]);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int i = e0 + lane; i < e1; i += 64) {
-            const uint32_t c = TT.pn_code[i];
-            if (c != null_code) Gt[c & kElem] = 0.0;
-        }
-        __builtin_amdgcn_wave_barrier();
+    VjpTile<KB> A, B;
+    vjp_fetch<KB>(A, 0, wid, ntiles, pnp, voff, xr, cres, lane);
+    for (int j = 0;; j += 2) {
+        vjp_fetch<KB>(B, j + 1, wid, ntiles, pnp, voff, xr, cres, lane);
+        vjp_work<KB, NBT>(A, acc, cres, null_code, gl, Gt, lane);
+        if (wid + kPnWaves * (j + 1) >= ntiles) break;
+        vjp_fetch<KB>(A, j + 2, wid, ntiles, pnp, voff, xr, cres, lane);
+        vjp_work<KB, NBT>(B, acc, cres, null_code, gl, Gt, lane);
+        if (wid + kPnWaves * (j + 2) >= ntiles) break;
     }
     const int ns = P.ns;
     const int64_t ns2 = (int64_t)ns * ns;
@@ -338,13 +384,13 @@ __device__ __forceinline__ void vjp_pn_class(const DevHam &P, const DevTiled &TT
         for (int bt = 0; bt < NBT; ++bt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int k = 16 * kb + Mma<double>::row(lane, r), B = 16 * bt + (lane & 15);
-                if (k >= kp || B >= nB) continue;
+                const int k = 16 * kb + Mma<double>::row(lane, r), Bl = 16 * bt + (lane & 15);
+                if (k >= kp || Bl >= nB) continue;
                 const int ck = P.p.ob_code[a0 + k];
                 const double v = (ck & 1) ? -acc[kb][bt][r] : acc[kb][bt][r];
                 if (v == 0.0) continue;
                 const int la = P.cls_ops[P.cls_off[q] + (ck >> 1)];
-                const int lb = P.cls_ops[P.cls_off[qn] + B];
+                const int lb = P.cls_ops[P.cls_off[qn] + Bl];
                 const int a = la / ns, c = la % ns, b = lb / ns, d = lb % ns;
                 atomicAdd(&d_v_pn[((int64_t)a * ns + b) * ns2 + (int64_t)c * ns + d], v);
             }
@@ -353,12 +399,13 @@ __device__ __forceinline__ void vjp_pn_class(const DevHam &P, const DevTiled &TT
 template <int KB>
 __device__ __forceinline__ void vjp_pn_nbt(int nbt, const DevHam &P, const DevTiled &TT, int a0, int kp, int nB,
                                            int q, int qn, const int32_t *pnp, int ntiles, __amdgpu_buffer_rsrc_t xr,
-                                           const double *gl, double *Gt, int wid, int lane, double *d_v_pn) {
+                                           __amdgpu_buffer_rsrc_t cres, const double *gl, double *Gt, int wid,
+                                           int lane, double *d_v_pn) {
     switch (nbt) {
-        case 1: vjp_pn_class<KB, 1>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
-        case 2: vjp_pn_class<KB, 2>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
-        case 3: vjp_pn_class<KB, 3>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
-        default: vjp_pn_class<KB, 4>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn); break;
+        case 1: vjp_pn_class<KB, 1>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, cres, gl, Gt, wid, lane, d_v_pn); break;
+        case 2: vjp_pn_class<KB, 2>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, cres, gl, Gt, wid, lane, d_v_pn); break;
+        case 3: vjp_pn_class<KB, 3>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, cres, gl, Gt, wid, lane, d_v_pn); break;
+        default: vjp_pn_class<KB, 4>(P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, cres, gl, Gt, wid, lane, d_v_pn); break;
     }
 }
 
@@ -382,6 +429,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_pn_mfma(DevHam P, DevTiled 
     double *Gt = Gall + wid * kPnTile * kPnRStride;
     const __amdgpu_buffer_rsrc_t xr =
         __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)sizeof(double)), kBufFlags);
+    const __amdgpu_buffer_rsrc_t cres =
+        __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn_code, (short)0, (int)(TT.n_pn_code * 4), kBufFlags);
     const int nq = P.nq, ntl = TT.n_t16;
     for (int q = 0; q < nq; ++q) {
         const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q], a1 = P.p.ob_ptr[(int64_t)ip * nq + q + 1];
@@ -393,9 +442,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_pn_mfma(DevHam P, DevTiled 
         const int32_t *pnp = TT.pn_ptr + ((int64_t)s * nq + qn) * ntl;
         const int kp = a1 - a0, nbt = (nB + 15) >> 4;
         if (kp > 16)
-            vjp_pn_nbt<2>(nbt, P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn);
+            vjp_pn_nbt<2>(nbt, P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, cres, gl, Gt, wid, lane, d_v_pn);
         else
-            vjp_pn_nbt<1>(nbt, P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, gl, Gt, wid, lane, d_v_pn);
+            vjp_pn_nbt<1>(nbt, P, TT, a0, kp, nB, q, qn, pnp, ntiles, xr, cres, gl, Gt, wid, lane, d_v_pn);
     }
 }
 
