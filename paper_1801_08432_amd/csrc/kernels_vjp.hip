@@ -44,13 +44,15 @@ __global__ __launch_bounds__(kT) void k_zero(double *p, int n) {
     if (i < n) p[i] = 0.0;
 }
 
-// Proton side, one block per destination proton SD ip: row dots against every
-// source row of its two-body entries (diagonal included), the diagonal row dot
-// for the proton single-particle energies, and the per-element products for
-// the neutron diagonal (column sums, atomically).
+// Proton side, one block per destination proton SD ip: the diagonal row dot
+// (proton single-particle energies and diagonal two-body labels), the
+// per-element products for the neutron diagonal (column sums, atomically),
+// and, with with_off, row dots against every source row of its off-diagonal
+// two-body entries (used when the tiled tables are not available;
+// k_vjp_sddmm<false> otherwise).
 __global__ __launch_bounds__(kT) void k_vjp_proton(DevHam P, const double *__restrict__ x,
                                                    const double *__restrict__ g, double *d_spe_p,
-                                                   double *d_v_pp, double *dcol_n) {
+                                                   double *d_v_pp, double *dcol_n, int with_off) {
     __shared__ double lds[kT / 64];
     const int ip = blockIdx.x;
     const int s = P.p_sector[ip];
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(kT) void k_vjp_proton(DevHam P, const double *__res
                 atomicAdd(&d_v_pp[code >> 1], (code & 1) ? -dd : dd);
             }
     }
-    if (!d_v_pp) return;
+    if (!d_v_pp || !with_off) return;
     for (int k = P.p.off_rowptr[ip]; k < P.p.off_rowptr[ip + 1]; ++k) {
         const int64_t sb = P.p_pstart[P.p.off_col[k]];
         double a = 0.0;
@@ -180,41 +182,50 @@ __global__ __launch_bounds__(kT) void k_vjp_pn(DevHam P, const double *__restric
     }
 }
 
-// nn two-body densities as a sampled product: in a basis sector s the entry
-// connecting neutron column cs to cd needs D[cd, cs] = sum_r g[r, cd] x[r, cs]
-// over the sector's proton rows, i.e. D = G_s^T X_s (G_s, X_s the row-major
-// np_s x nn_s blocks) sampled on the pattern of the neutron two-body jumps;
-// d_v_nn[label] += phase D[cd, cs] for every jump of the entry. One wave per
-// 32 x 32 tile of D that holds an entry: the sum over rows runs on the matrix
-// cores (16x16x4 float64, A = G^T, B = X, both read as 16-element row
-// segments), the tile goes to LDS, and the wave samples it at the ELL entries
-// of its 32 destination columns.
+// Two-body densities of one species as a sampled product. In a basis sector
+// (the row-major np x nn blocks G and X of g and x):
+//   neutrons (NEUT): the entry from column cs to column cd needs
+//     D[cd, cs] = sum_r g[r, cd] x[r, cs], D = G^T X;
+//   protons: the entry from row rs to row rd needs
+//     D[rd, rs] = sum_c g[rd, c] x[rs, c], D = G X^T;
+// sampled on the pattern of the species' two-body jumps, and
+// d_v[label] += phase D for every jump of the entry. One wave per 32 x 32
+// tile of D that holds an entry: the sum runs on the matrix cores (16x16x4
+// float64), the tile goes to LDS, and the wave samples it at the ELL entries
+// (the tables of the tiled apply) of its 32 destination columns or rows.
 constexpr int kSd = 32;
 
-__global__ __launch_bounds__(64) void k_vjp_nn_sddmm(DevHam P, DevTiled TT, const double *__restrict__ x,
-                                                     const double *__restrict__ g, double *d_v_nn) {
+template <bool NEUT>
+__global__ __launch_bounds__(64) void k_vjp_sddmm(DevHam P, DevTiled TT, const double *__restrict__ x,
+                                                  const double *__restrict__ g, double *d_v) {
     __shared__ double Dt[kSd][kSd + 1];
     int b = blockIdx.x, s = 0;
     for (; s < P.n_sectors; ++s) {
-        const int nb = (P.sec_nn[s] + kSd - 1) / kSd;
+        const int m = NEUT ? P.sec_nn[s] : P.sec_np[s];
+        const int nb = (m + kSd - 1) / kSd;
         if (b < nb * nb) break;
         b -= nb * nb;
     }
     if (s >= P.n_sectors) return;   // uniform
     const int np = P.sec_np[s], nn = P.sec_nn[s];
-    const int nbk = (nn + kSd - 1) / kSd;
-    const int cd0 = kSd * (b / nbk), cs0 = kSd * (b % nbk);
+    const int m = NEUT ? nn : np;   // D is m x m
+    const int K = NEUT ? np : nn;   // summed index
+    const int nbk = (m + kSd - 1) / kSd;
+    const int d0 = kSd * (b / nbk), s0 = kSd * (b % nbk);
     const int64_t off = P.sec_off[s];
-    const int E = TT.nn_ell_E[s];
-    const int64_t eb = TT.nn_ell_base[s];
+    const int E = NEUT ? TT.nn_ell_E[s] : TT.pp_ell_E[s];
+    const int64_t eb = NEUT ? TT.nn_ell_base[s] : TT.pp_ell_base[s];
+    const int32_t *esrc = NEUT ? TT.nn_ell_src : TT.pp_ell_src;
+    const int32_t *eent = NEUT ? TT.nn_ell_ent : TT.pp_ell_ent;
+    const DevSpecies &sp = NEUT ? P.n : P.p;
     const int lane = threadIdx.x;
     // skip tiles that no entry samples
     bool hit = false;
     for (int i = lane; i < kSd * E; i += 64) {
-        const int cd = cd0 + (i & (kSd - 1));
-        if (cd >= nn) continue;
-        const int64_t k = eb + (int64_t)(i / kSd) * nn + cd;
-        if (TT.nn_ell_ent[k] >= 0 && TT.nn_ell_src[k] >= cs0 && TT.nn_ell_src[k] < cs0 + kSd) hit = true;
+        const int dd = d0 + (i & (kSd - 1));
+        if (dd >= m) continue;
+        const int64_t k = eb + (int64_t)(i / kSd) * m + dd;
+        if (eent[k] >= 0 && esrc[k] >= s0 && esrc[k] < s0 + kSd) hit = true;
     }
     if (__ballot(hit) == 0) return;   // uniform
     doublex4 acc[2][2];
@@ -222,18 +233,22 @@ __global__ __launch_bounds__(64) void k_vjp_nn_sddmm(DevHam P, DevTiled TT, cons
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = Mma<double>::zero();
-    // lane: row r0 + lane / 16 of each 4-row step, column 16 i + lane % 16 of the tile
+    // lane: summed index k0 + lane / 16 of each step of 4, tile index 16 i + lane % 16
     const int cl = lane & 15;
-    for (int r0 = 0; r0 < np; r0 += 4) {
-        const int r = r0 + (lane >> 4);
-        const double *gr = g + off + (int64_t)r * nn;
-        const double *xr = x + off + (int64_t)r * nn;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int kk = k0 + (lane >> 4);
         double a[2], bv[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int cd = cd0 + 16 * i + cl, cs = cs0 + 16 * i + cl;
-            a[i] = r < np && cd < nn ? gr[cd] : 0.0;
-            bv[i] = r < np && cs < nn ? xr[cs] : 0.0;
+            const int dd = d0 + 16 * i + cl, ss = s0 + 16 * i + cl;
+            const bool ok = kk < K;
+            if (NEUT) {   // G^T[dd][kk] = g[kk, dd], X[kk][ss] = x[kk, ss]
+                a[i] = ok && dd < m ? g[off + (int64_t)kk * nn + dd] : 0.0;
+                bv[i] = ok && ss < m ? x[off + (int64_t)kk * nn + ss] : 0.0;
+            } else {      // G[dd][kk] = g[dd, kk], X^T[kk][ss] = x[ss, kk]
+                a[i] = ok && dd < m ? g[off + (int64_t)dd * nn + kk] : 0.0;
+                bv[i] = ok && ss < m ? x[off + (int64_t)ss * nn + kk] : 0.0;
+            }
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -248,16 +263,16 @@ __global__ __launch_bounds__(64) void k_vjp_nn_sddmm(DevHam P, DevTiled TT, cons
             for (int q = 0; q < 4; ++q) Dt[16 * i + Mma<double>::row(lane, q)][16 * j + cl] = acc[i][j][q];
     __syncthreads();
     for (int i = lane; i < kSd * E; i += 64) {
-        const int c = i & (kSd - 1), cd = cd0 + c;
-        if (cd >= nn) continue;
-        const int64_t k = eb + (int64_t)(i / kSd) * nn + cd;
-        const int ent = TT.nn_ell_ent[k];
-        const int src = TT.nn_ell_src[k];
-        if (ent < 0 || src < cs0 || src >= cs0 + kSd) continue;
-        const double dv = Dt[c][src - cs0];
-        for (int j = P.n.off_j0[ent]; j < P.n.off_j1[ent]; ++j) {
-            const int code = P.n.code2[j];
-            atomicAdd(&d_v_nn[code >> 1], (code & 1) ? -dv : dv);
+        const int c = i & (kSd - 1), dd = d0 + c;
+        if (dd >= m) continue;
+        const int64_t k = eb + (int64_t)(i / kSd) * m + dd;
+        const int ent = eent[k];
+        const int src = esrc[k];
+        if (ent < 0 || src < s0 || src >= s0 + kSd) continue;
+        const double dv = Dt[c][src - s0];
+        for (int j = sp.off_j0[ent]; j < sp.off_j1[ent]; ++j) {
+            const int code = sp.code2[j];
+            atomicAdd(&d_v[code >> 1], (code & 1) ? -dv : dv);
         }
     }
 }
@@ -543,6 +558,17 @@ void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const doub
                 double *d_spe_n, double *d_v_pp, double *d_v_nn, double *d_v_pn, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     if (dx) launch_apply(h, FOTCI_MODE_F64, g, dx, stream);
+    const DevTiled &tt = h->dev_tiled;
+    // off-diagonal pp / nn densities as sampled products when the tiled tables exist
+    auto sddmm_tiles = [&](bool neut) {
+        int64_t tiles = 0;
+        for (size_t si = 0; si < h->tc.sec_nn.size(); ++si) {
+            const int64_t mb = ((neut ? h->tc.sec_nn[si] : h->tc.sec_np[si]) + kSd - 1) / kSd;
+            tiles += mb * mb;
+        }
+        return tiles;
+    };
+    const bool sd_p = d_v_pp && tt.ok, sd_n = d_v_nn && tt.ok;
     double *dcol = nullptr;
     const bool need_n = d_spe_n || d_v_nn;
     if (need_n) {
@@ -551,15 +577,17 @@ void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const doub
         hipLaunchKernelGGL(k_zero, dim3((d.n.n_sd + kT - 1) / kT), dim3(kT), 0, st, dcol, d.n.n_sd);
     }
     if (d_spe_p || d_v_pp || need_n)
-        hipLaunchKernelGGL(k_vjp_proton, dim3(d.p.n_sd), dim3(kT), 0, st, d, x, g, d_spe_p, d_v_pp, dcol);
-    const DevTiled &tt = h->dev_tiled;
-    const bool sddmm = d_v_nn && tt.ok;
+        hipLaunchKernelGGL(k_vjp_proton, dim3(d.p.n_sd), dim3(kT), 0, st, d, x, g, d_spe_p, d_v_pp, dcol,
+                           sd_p ? 0 : 1);
     if (need_n) hipLaunchKernelGGL(k_vjp_neutron, dim3(d.n.n_sd), dim3(kT), 0, st, d, x, g, (const double *)dcol,
-                                   d_spe_n, d_v_nn, sddmm ? 0 : 1);
-    if (sddmm) {
-        int64_t tiles = 0;
-        for (int nn : h->tc.sec_nn) tiles += (int64_t)((nn + kSd - 1) / kSd) * ((nn + kSd - 1) / kSd);
-        if (tiles > 0) hipLaunchKernelGGL(k_vjp_nn_sddmm, dim3((unsigned)tiles), dim3(64), 0, st, d, tt, x, g, d_v_nn);
+                                   d_spe_n, d_v_nn, sd_n ? 0 : 1);
+    if (sd_p) {
+        const int64_t tiles = sddmm_tiles(false);
+        if (tiles > 0) hipLaunchKernelGGL(k_vjp_sddmm<false>, dim3((unsigned)tiles), dim3(64), 0, st, d, tt, x, g, d_v_pp);
+    }
+    if (sd_n) {
+        const int64_t tiles = sddmm_tiles(true);
+        if (tiles > 0) hipLaunchKernelGGL(k_vjp_sddmm<true>, dim3((unsigned)tiles), dim3(64), 0, st, d, tt, x, g, d_v_nn);
     }
     if (d_v_pn) {
         const DevTiled &t = tt;
