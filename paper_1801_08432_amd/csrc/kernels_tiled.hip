@@ -20,14 +20,15 @@
 //            over the K_p proton one-body jumps (ip_k -> ip', label A_k) is a
 //            dense contraction on the matrix cores (M = neutron labels B, N =
 //            source neutron columns jn, K = proton jumps); each wave takes
-//            16-column source tiles, keeps its R tile in LDS, and the neutron
+//            32-column source tiles, keeps its R tile in LDS, and the neutron
 //            one-body jumps whose source lies in the tile (pre-grouped by
-//            tile, read coalesced) add phase_l R[B_l, jn_l] into the output
-//            row held in LDS.
+//            tile, read coalesced) add phase_l R[B_l, jn_l] into the wave's
+//            output row held in LDS.
 //            This is the proton-first grouping of sum_{A,B} V_AB P_A X N_B^T:
 //            the contraction over B is dense, so the matrix cores execute
-//            about n_B / (neutron jumps per column) ~ 5 times the useful
-//            multiply-adds of the pn part. Adds to y.
+//            about 6.5 times the useful multiply-adds of the pn part. Adds to
+//            y. With a vector stride NB the same kernel serves the pn part of
+//            the block apply, one vector per workgroup.
 #include <hip/hip_runtime.h>
 
 #include "tiled_common.h"
