@@ -7,8 +7,12 @@ events between its kernels on the launch stream during the timed steps, which
 gives the duration of the dominant kernel (pn) for the roofline object. After
 the timed steps the script runs the Lanczos comparison the metric asks for
 (float32-vector path against the plain float64 path, lowest 10 of 200
-iterations; the tiled float64 path beside them) and times the CPU oracle on a
-bounded sample of rows. One JSON line is printed.
+iterations; the tiled float64 path beside them), thick-restart Lanczos in
+float32 and float64, the block apply_H (blocks of 2, 4, 8) and block Lanczos,
+the one-body densities, the adjoint (dx and every label density), a J-coupled
+interaction with good-J checks, and times the CPU oracle on a bounded sample
+of rows (each leg can be switched off with its --no-* flag). One JSON line is
+printed.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
