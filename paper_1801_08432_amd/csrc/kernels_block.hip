@@ -119,7 +119,9 @@ __global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *_
     const RowT *xb = reinterpret_cast<const RowT *>(x);
     RowT *yb = reinterpret_cast<RowT *>(y);
     const int tid = threadIdx.x;
-    const int s = TT.ct_sec[blockIdx.x], c0t = TT.ct_c0[blockIdx.x];
+    const int tile = pp_tile_of<pp_line_group<T, NB>()>(blockIdx.x);
+    if (tile >= TT.n_ctiles) return;
+    const int s = TT.ct_sec[tile], c0t = TT.ct_c0[tile];
     const int np = P.sec_np[s], nn = P.sec_nn[s];
     const int64_t off = P.sec_off[s];
     const int E = TT.pp_ell_E[s];
@@ -192,19 +194,20 @@ void launch_nn_blk(int rt, const DevHam &d, const DevTiled &t, const T *x, T *y,
 
 template <typename T, int NB>
 void launch_pp_blk(int ct, const DevHam &d, const DevTiled &t, const T *x, T *y, size_t lds, hipStream_t st) {
+    const dim3 grid(pp_grid(t.n_ctiles, pp_line_group<T, NB>()));
     if constexpr (4 * NB <= kTile) {
         if (ct == 4) {
-            hipLaunchKernelGGL((k_pp_blk<T, 4, NB>), dim3(t.n_ctiles), dim3(kT), lds, st, d, t, x, y);
+            hipLaunchKernelGGL((k_pp_blk<T, 4, NB>), grid, dim3(kT), lds, st, d, t, x, y);
             return;
         }
     }
     if constexpr (2 * NB <= kTile) {
         if (ct == 2) {
-            hipLaunchKernelGGL((k_pp_blk<T, 2, NB>), dim3(t.n_ctiles), dim3(kT), lds, st, d, t, x, y);
+            hipLaunchKernelGGL((k_pp_blk<T, 2, NB>), grid, dim3(kT), lds, st, d, t, x, y);
             return;
         }
     }
-    hipLaunchKernelGGL((k_pp_blk<T, 1, NB>), dim3(t.n_ctiles), dim3(kT), lds, st, d, t, x, y);
+    hipLaunchKernelGGL((k_pp_blk<T, 1, NB>), grid, dim3(kT), lds, st, d, t, x, y);
 }
 
 template <typename T, int NB>

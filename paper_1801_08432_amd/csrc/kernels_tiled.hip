@@ -106,7 +106,9 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Xl = reinterpret_cast<T *>(smem_raw);   // Xl[r * CT + c]
     const int tid = threadIdx.x;
-    const int s = TT.ct_sec[blockIdx.x], c0t = TT.ct_c0[blockIdx.x];
+    const int tile = pp_tile_of<pp_line_group<T, 1>()>(blockIdx.x);
+    if (tile >= TT.n_ctiles) return;
+    const int s = TT.ct_sec[tile], c0t = TT.ct_c0[tile];
     const int np = P.sec_np[s], nn = P.sec_nn[s];
     const int64_t off = P.sec_off[s];
     const int E = TT.pp_ell_E[s];
@@ -422,11 +424,12 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[1], st), "event");
     const int ct = pick_tile(t.max_np, sizeof(T));
     const size_t lds_pp = (size_t)ct * t.max_np * sizeof(T);
+    const dim3 gpp(pp_grid(t.n_ctiles, pp_line_group<T, 1>()));
     switch (ct) {
-        case 8: hipLaunchKernelGGL((k_pp<T, 8>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
-        case 4: hipLaunchKernelGGL((k_pp<T, 4>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
-        case 2: hipLaunchKernelGGL((k_pp<T, 2>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
-        default: hipLaunchKernelGGL((k_pp<T, 1>), dim3(t.n_ctiles), dim3(kT), lds_pp, st, d, t, x, y); break;
+        case 8: hipLaunchKernelGGL((k_pp<T, 8>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
+        case 4: hipLaunchKernelGGL((k_pp<T, 4>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
+        case 2: hipLaunchKernelGGL((k_pp<T, 2>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
+        default: hipLaunchKernelGGL((k_pp<T, 1>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
     }
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[2], st), "event");
     launch_pn_nb<T, 1>(d, t, x, y, st);

@@ -146,6 +146,24 @@ struct PnClass {
     uint32_t null_code;       // padding entry of the gather lists
 };
 
+// Workgroups are dealt to the 8 XCDs in turn (slot b runs on XCD b % 8). A
+// column tile of the pp kernels reads and updates kTile columns (times NB
+// vectors) of each row of its sector, so G consecutive tiles share the
+// 128-byte lines of x and y; pp_tile_of gives each run of G tiles to one XCD,
+// whose L2 then serves every line to all of them instead of each XCD fetching
+// it. The grid is padded to a multiple of 8 * G; slots past the last tile
+// return.
+template <typename T, int NB>
+constexpr int pp_line_group() {
+    return kTile * NB * (int)sizeof(T) >= 128 ? 1 : 128 / (kTile * NB * (int)sizeof(T));
+}
+template <int G>
+__device__ __forceinline__ int pp_tile_of(int b) {
+    const int xcd = b & 7, s8 = b >> 3;
+    return (s8 / G) * (8 * G) + xcd * G + s8 % G;
+}
+inline unsigned pp_grid(int n_tiles, int g) { return (unsigned)((n_tiles + 8 * g - 1) / (8 * g) * (8 * g)); }
+
 // Largest tile (8, 4, 2 or 1 rows or columns) whose staged slab of max_len
 // elements of elem bytes each fits kLdsTile.
 inline int pick_tile(int max_len, int elem) {
