@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Xl = reinterpret_cast<T *>(smem_raw);   // Xl[r * CT + c]
     const int tid = threadIdx.x;
-    const int tile = pp_tile_of<pp_line_group<T, 1>()>(blockIdx.x);
+    const int tile = pp_tile_of<kPpRunLines * pp_line_group<T, 1>()>(blockIdx.x);
     if (tile >= TT.n_ctiles) return;
     const int s = TT.ct_sec[tile], c0t = TT.ct_c0[tile];
     const int np = P.sec_np[s], nn = P.sec_nn[s];
@@ -424,7 +424,7 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[1], st), "event");
     const int ct = pick_tile(t.max_np, sizeof(T));
     const size_t lds_pp = (size_t)ct * t.max_np * sizeof(T);
-    const dim3 gpp(pp_grid(t.n_ctiles, pp_line_group<T, 1>()));
+    const dim3 gpp(pp_grid(t.n_ctiles, kPpRunLines * pp_line_group<T, 1>()));
     switch (ct) {
         case 8: hipLaunchKernelGGL((k_pp<T, 8>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
         case 4: hipLaunchKernelGGL((k_pp<T, 4>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
