@@ -16,7 +16,10 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;      // threads per workgroup (4 waves)
 constexpr int kTile = 8;     // rows (nn kernel) / columns (pp kernel) per tile
-constexpr int kLdsTile = 131072;  // bytes of LDS for a staged tile (gfx950: up to 160 KiB per workgroup)
+// Bytes of LDS for a staged tile: at most half of a CU's 160 KiB, so that two
+// workgroups share a CU (a 106 KiB float64 slab left one per CU, 4 waves,
+// and ran the nn kernel at 0.79 ms against 0.58 ms with half the rows).
+constexpr int kLdsTile = 81920;
 
 template <typename T>
 struct Mma;
