@@ -291,7 +291,7 @@ typedef struct {
     int32_t mode;          /* FOTCI_MODE_* */
     int32_t refine;        /* 1: float64 Rayleigh-quotient refinement of the Ritz vectors */
     int32_t reorth;        /* FOTCI_REORTH_* */
-    double tol;            /* convergence threshold (> 0) on the residual estimate */
+    double tol;            /* convergence threshold (> 0), relative to max(1, |E|) */
 } fotci_trlan_opts;
 
 /* Bytes of device workspace fotci_lanczos_thick_restart needs (negative
@@ -302,9 +302,15 @@ int64_t fotci_trlan_workspace_bytes(const fotci_ham *h, const fotci_trlan_opts *
  * pivot: device float64 [dim]; work: device workspace (256-byte aligned) of
  * at least the queried size; evals, resid: host [n_keep]; evecs: device
  * float64 [n_keep*dim] Ritz vectors or NULL; stats: host int32[3] =
- * {restarts, apply_H calls in the cycles, converged (0/1)} or NULL. A run
- * that exhausts max_restarts returns FOTCI_OK with stats[2] = 0 and the
- * current Ritz pairs. Synchronous. FOTCI_ENOTCONV if the Krylov space breaks
+ * {restarts, apply_H calls in the cycles, converged (0/1)} or NULL. The
+ * cycles stop when the recurrence's estimate meets tol (or max_restarts is
+ * exhausted); converged is then 1 only if every returned resid[mu] (the true
+ * ||H y - E y|| of the float64 Ritz vector, H applied in float64) is
+ * <= tol * max(1, |E_mu|). With FOTCI_MODE_F32 the stored basis limits that
+ * residual to roughly 1e-7 * ||H|| (float32 rounding of the vectors), so a
+ * tol below that returns converged = 0 with the best pairs found. A run that
+ * exhausts max_restarts returns FOTCI_OK with stats[2] = 0 and the current
+ * Ritz pairs. Synchronous. FOTCI_ENOTCONV if the Krylov space breaks
  * down before n_keep Ritz values exist.
  */
 int fotci_lanczos_thick_restart(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivot, void *work,

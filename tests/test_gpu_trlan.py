@@ -81,3 +81,7 @@ def test_thick_restart_f32_vs_f64_pf_4p4n():
     _say("[trlan f32 vs f64] rel", rel, "restarts", r64["restarts"], r32["restarts"])
     assert r64["converged"] and r64["restarts"] >= 1
     assert np.all(rel <= 1e-5)
+    # the flag reports the true float64 residual of the returned vectors
+    for r in (r64, r32):
+        if r["converged"]:
+            assert np.all(r["resid"] <= 1e-9 * np.maximum(1.0, np.abs(r["evals"])))
