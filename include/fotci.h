@@ -216,6 +216,25 @@ int fotci_apply_H(const fotci_ham *h, int32_t mode, const void *x, void *y, void
 int fotci_apply_H_block(const fotci_ham *h, int32_t mode, int32_t n_block, const void *x, void *y, void *stream);
 
 /*
+ * fotci_apply_H_vjp_static -- fotci_apply_H_vjp for callers that cannot
+ * allocate or must not depend on per-call device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and accumulation rules as fotci_apply_H_vjp; the
+ * per-neutron-SD column sums it needs go to a static device array of the
+ * library (65,536 doubles = 512 KiB per GPU, held from the first call on a
+ * device until the process ends) instead of the Hamiltonian's workspace. It
+ * calls no device or host allocator; the kernels clear the array before use.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (different streams or threads) race and give wrong results.
+ * FOTCI_EINVAL if the basis has more than 65,536 neutron SDs (use
+ * fotci_apply_H_vjp), FOTCI_ESTATE if the Hamiltonian is not uploaded,
+ * FOTCI_EHIP if the array's device address cannot be obtained.
+ */
+int fotci_apply_H_vjp_static(const fotci_ham *h, const double *x, const double *g, double *dx,
+                             double *d_spe_p, double *d_spe_n, double *d_v_pp, double *d_v_nn,
+                             double *d_v_pn, void *stream);
+
+/*
  * fotci_one_body_density -- m-scheme one-body transition densities of two
  * vectors of the basis (Ch. 5, "One-body density matrices", in the
  * proton-neutron form the reduced densities are coupled from):

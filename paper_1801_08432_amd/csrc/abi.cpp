@@ -202,6 +202,22 @@ int fotci_apply_H_vjp(const fotci_ham *h, const double *x, const double *g, doub
     });
 }
 
+int fotci_apply_H_vjp_static(const fotci_ham *h, const double *x, const double *g, double *dx, double *d_spe_p,
+                             double *d_spe_n, double *d_v_pp, double *d_v_nn, double *d_v_pn, void *stream) {
+    return guard([&] {
+        if (!h || !x || !g) fail(FOTCI_EINVAL, "NULL argument");
+        const int64_t n_nsd = (int64_t)h->j->b->n.sd.size();
+        if (n_nsd > kStaticNcolMax)
+            fail(FOTCI_EINVAL, "fotci_apply_H_vjp_static: " + std::to_string(n_nsd) +
+                                   " neutron SDs exceed the static scratch of " + std::to_string(kStaticNcolMax) +
+                                   " (use fotci_apply_H_vjp)");
+        if (!h->uploaded) fail(FOTCI_ESTATE, "Hamiltonian not uploaded");
+        double *ncol = static_ncol_scratch();
+        launch_vjp(h->dev, h, x, g, dx, d_spe_p, d_spe_n, d_v_pp, d_v_nn, d_v_pn, stream, ncol);
+        return FOTCI_OK;
+    });
+}
+
 int fotci_one_body_density(const fotci_ham *h, const double *g, const double *x, double *rho_p, double *rho_n,
                            void *stream) {
     return guard([&] {

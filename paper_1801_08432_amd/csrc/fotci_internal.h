@@ -259,9 +259,16 @@ void launch_apply_nb(const fotci_ham *h, int mode, int nb, const void *x, void *
 void build_tiled_tables(fotci_ham *h);
 void launch_one_body_density(const DevHam &d, const std::vector<int32_t> &h_sec_np, int q0, const double *g,
                              const double *x, double *rho_p, double *rho_n, void *stream);
+// ncol: device buffer of n_nsd doubles for the neutron column sums, or NULL
+// for the one in the Hamiltonian's workspace
 void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g,
                 double *dx, double *d_spe_p, double *d_spe_n, double *d_v_pp, double *d_v_nn,
-                double *d_v_pn, void *stream);
+                double *d_v_pn, void *stream, double *ncol = nullptr);
+// The allocation-free adjoint's scratch: a static device array of
+// kStaticNcolMax doubles; its address on the current device (looked up once
+// per device).
+constexpr int kStaticNcolMax = 1 << 16;
+double *static_ncol_scratch();
 int64_t lanczos_bytes(const fotci_ham *h, const fotci_lanczos_opts *o);
 void lanczos_run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, void *work,
                  int64_t work_bytes, double *evals, double *resid, double *evecs, double *alpha,

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "tiled_common.h"
 
@@ -554,8 +555,31 @@ void launch_one_body_density(const DevHam &d, const std::vector<int32_t> &h_sec_
     hip_check(hipGetLastError(), "one-body density launch");
 }
 
+// Column-sum scratch of fotci_apply_H_vjp_static: one array per GPU (each
+// device holds its own copy of a __device__ variable), shared by every call on
+// that GPU and kept until the process ends. In host code `scratch` names a
+// host-side stand-in; its device address comes from hipGetSymbolAddress, once
+// per device, and only that address is handed to kernels.
+static __device__ __align__(256) double scratch[kStaticNcolMax];
+
+double *static_ncol_scratch() {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) fail(FOTCI_EINVAL, "device ordinal out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        ptr[dev] = (double *)p;
+    }
+    return ptr[dev];
+}
+
 void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const double *g, double *dx, double *d_spe_p,
-                double *d_spe_n, double *d_v_pp, double *d_v_nn, double *d_v_pn, void *stream) {
+                double *d_spe_n, double *d_v_pp, double *d_v_nn, double *d_v_pn, void *stream, double *ncol) {
     hipStream_t st = (hipStream_t)stream;
     if (dx) launch_apply(h, FOTCI_MODE_F64, g, dx, stream);
     const DevTiled &tt = h->dev_tiled;
@@ -572,8 +596,9 @@ void launch_vjp(const DevHam &d, const fotci_ham *h, const double *x, const doub
     double *dcol = nullptr;
     const bool need_n = d_spe_n || d_v_nn;
     if (need_n) {
-        // column sums of g o x per neutron SD, in the Hamiltonian's workspace
-        dcol = d.scratch_ncol;
+        // column sums of g o x per neutron SD: in the Hamiltonian's workspace,
+        // or in the caller-chosen buffer (the static scratch)
+        dcol = ncol ? ncol : d.scratch_ncol;
         hipLaunchKernelGGL(k_zero, dim3((d.n.n_sd + kT - 1) / kT), dim3(kT), 0, st, dcol, d.n.n_sd);
     }
     if (d_spe_p || d_v_pp || need_n)

@@ -27,7 +27,7 @@ EXPORTED = [
     "fotci_last_error", "fotci_version", "fotci_build_basis", "fotci_free_basis", "fotci_basis_info",
     "fotci_basis_export", "fotci_build_jumps", "fotci_free_jumps", "fotci_jumps_count", "fotci_jumps_export",
     "fotci_set_interaction", "fotci_free_ham", "fotci_ham_set_values", "fotci_ham_workspace_bytes",
-    "fotci_ham_upload", "fotci_apply_H", "fotci_apply_H_vjp", "fotci_one_body_density",
+    "fotci_ham_upload", "fotci_apply_H", "fotci_apply_H_vjp", "fotci_apply_H_vjp_static", "fotci_one_body_density",
     "fotci_lanczos_workspace_bytes",
     "fotci_lanczos_lowest", "fotci_trlan_workspace_bytes", "fotci_lanczos_thick_restart",
     "fotci_ham_op_counts", "fotci_ham_pn_work", "fotci_ham_set_pn_private_rows",
@@ -93,6 +93,7 @@ def lib():
         "fotci_ham_upload": (ctypes.c_int, [P, P, I64, P]),
         "fotci_apply_H": (ctypes.c_int, [P, I32, P, P, P]),
         "fotci_apply_H_vjp": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P]),
+        "fotci_apply_H_vjp_static": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P]),
         "fotci_one_body_density": (ctypes.c_int, [P, P, P, P, P, P]),
         "fotci_lanczos_workspace_bytes": (I64, [P, P]),
         "fotci_lanczos_lowest": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P, P]),
@@ -286,8 +287,10 @@ class Hamiltonian:
         _check(lib().fotci_apply_H_block(self._h, m, int(x.shape[1]), _dev_ptr(x), _dev_ptr(y), _stream(stream)))
         return y
 
-    def vjp(self, x, g, want_dx=True, stream=None):
-        """(dx, grads) of L = <g, H x>: dx = H g and label-wise densities."""
+    def vjp(self, x, g, want_dx=True, stream=None, static_scratch=False):
+        """(dx, grads) of L = <g, H x>: dx = H g and label-wise densities.
+        static_scratch: call fotci_apply_H_vjp_static (the library's static
+        device scratch instead of the Hamiltonian's workspace)."""
         import torch
         ns = self.basis.n_states
         npairs = ns * (ns - 1) // 2
@@ -299,9 +302,10 @@ class Hamiltonian:
                      v_nn=torch.zeros(npairs, npairs, dtype=torch.float64, device=dev),
                      v_pn=torch.zeros(ns * ns, ns * ns, dtype=torch.float64, device=dev))
         dx = torch.empty_like(x) if want_dx else None
-        _check(lib().fotci_apply_H_vjp(self._h, _dev_ptr(x), _dev_ptr(g), _dev_ptr(dx), _dev_ptr(grads["eps_p"]),
-                                       _dev_ptr(grads["eps_n"]), _dev_ptr(grads["v_pp"]), _dev_ptr(grads["v_nn"]),
-                                       _dev_ptr(grads["v_pn"]), _stream(stream)))
+        fn = lib().fotci_apply_H_vjp_static if static_scratch else lib().fotci_apply_H_vjp
+        _check(fn(self._h, _dev_ptr(x), _dev_ptr(g), _dev_ptr(dx), _dev_ptr(grads["eps_p"]),
+                  _dev_ptr(grads["eps_n"]), _dev_ptr(grads["v_pp"]), _dev_ptr(grads["v_nn"]),
+                  _dev_ptr(grads["v_pn"]), _stream(stream)))
         return dx, grads
 
     def one_body_density(self, g, x, stream=None):
