@@ -161,8 +161,10 @@ struct DevTiled {
     int32_t n_rtiles, n_ctiles, rt_rows, ct_cols;
     // pn neutron gather lists grouped by (destination sector, neutron class, 16-column source tile)
     const int32_t *pn_ptr;       // [(n_sectors*nq)*n_t16 + 1]
-    const uint32_t *pn_code;     // (phase < 0) << 31 | dst col << kPnRBits | R element; rounds of 64 entries
-                                 // with distinct destinations, padded with pn_null (R element 0, dst col max_nn)
+    const uint32_t *pn_code;     // (phase < 0) << 31 | last << 30 | dst col << kPnRBits | R element; rounds of
+                                 // 64 entries, each destination owned by one lane (its entries consecutive
+                                 // there, `last` on the final one), padded with pn_null (R element 0, dst
+                                 // col max_nn, not last)
     int64_t n_pn_code;           // entries of pn_code (a multiple of 64)
     uint32_t pn_null;            // padding code
     int32_t n_t16;               // tiles per sector slot (ceil(max nn / kPnTile))
@@ -180,7 +182,8 @@ struct DevTiled {
 constexpr int kPnTile = 32;                 // source columns per tile (a multiple of 16)
 constexpr int kPnRStride = 68;
 constexpr int kPnRBits = 12;                // kPnTile * kPnRStride <= 1 << kPnRBits
-constexpr int kPnDstBits = 31 - kPnRBits;
+constexpr int kPnDstBits = 30 - kPnRBits;   // bit 30: last entry of its destination in its lane
+constexpr uint32_t kPnFlush = 1u << 30;
 constexpr int kPnWaves = 2;                 // waves per pn workgroup
 
 struct HostTiled {

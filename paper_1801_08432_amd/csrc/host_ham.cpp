@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 #include "fotci_internal.h"
 
@@ -177,43 +178,55 @@ void build_tiled_tables(fotci_ham *h) {
         });
         for (size_t i : by_src) order[fill[slot(rec[i])]++] = i;
     }
-    // Pack each slot into rounds of 64 entries with distinct destination
-    // columns (one round = one LDS instruction of a wave, so no two lanes add
-    // to the same address); every round is padded to 64 entries with the
-    // null code, which adds R element 0 to the padding column max_nn.
+    // Pack each slot into rounds of 64 lanes in which every destination
+    // column is owned by one lane: its entries occupy consecutive rounds of
+    // that lane and the last one carries the flush bit, so the kernel sums
+    // them in a register and touches the output row once per destination
+    // and tile; no two lanes of a tile ever share a destination. Destinations
+    // go to the least-loaded lane, most entries first; rounds are padded to
+    // the busiest lane with the null code (R element 0, the spare column,
+    // no flush).
     const uint32_t null_code = (uint32_t)t.max_nn << kPnRBits;
     t.pn_ptr.assign(cnt.size(), 0);
     t.pn_code.clear();
-    std::vector<std::vector<uint32_t>> rounds;
-    std::vector<std::vector<uint32_t>> round_dst;
+    std::vector<std::pair<uint32_t, std::vector<uint32_t>>> bydst;
+    std::vector<std::vector<uint32_t>> lanes(64);
+    std::vector<int> load(64);
     for (size_t sl = 0; sl + 1 < cnt.size(); ++sl) {
         t.pn_ptr[sl] = (int64_t)t.pn_code.size();
-        rounds.clear();
-        round_dst.clear();
+        if (cnt[sl] == cnt[sl + 1]) continue;
+        bydst.clear();
+        std::map<uint32_t, size_t> where;
         for (int64_t k = cnt[sl]; k < cnt[sl + 1]; ++k) {
             const auto &r = rec[order[k]];
             const uint32_t dcol = (uint32_t)b->n.sd_local[r.dst];
             const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kTL);
             const uint32_t B = (uint32_t)cl.local_of[r.label];
-            // sign << 31 | destination column << 11 | R element (source offset in the tile, label B)
             const uint32_t code =
                 (r.phase < 0 ? 0x80000000u : 0u) | (dcol << kPnRBits) | (so * (uint32_t)kPnRStride + B);
-            size_t g = 0;
-            for (; g < rounds.size(); ++g) {
-                if (rounds[g].size() >= 64) continue;
-                if (std::find(round_dst[g].begin(), round_dst[g].end(), dcol) == round_dst[g].end()) break;
+            auto it = where.find(dcol);
+            if (it == where.end()) {
+                where[dcol] = bydst.size();
+                bydst.push_back({dcol, {code}});
+            } else {
+                bydst[it->second].second.push_back(code);
             }
-            if (g == rounds.size()) {
-                rounds.emplace_back();
-                round_dst.emplace_back();
-            }
-            rounds[g].push_back(code);
-            round_dst[g].push_back(dcol);
         }
-        for (size_t g = 0; g < rounds.size(); ++g) {
-            for (uint32_t c : rounds[g]) t.pn_code.push_back(c);
-            for (size_t p = rounds[g].size(); p < 64; ++p) t.pn_code.push_back(null_code);
+        std::stable_sort(bydst.begin(), bydst.end(), [](const auto &x, const auto &y) {
+            if (x.second.size() != y.second.size()) return x.second.size() > y.second.size();
+            return x.first < y.first;
+        });
+        for (auto &l : lanes) l.clear();
+        std::fill(load.begin(), load.end(), 0);
+        for (auto &dl : bydst) {
+            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (size_t i = 0; i < dl.second.size(); ++i)
+                lanes[l].push_back(dl.second[i] | (i + 1 == dl.second.size() ? kPnFlush : 0u));
+            load[l] += (int)dl.second.size();
         }
+        const int nr = *std::max_element(load.begin(), load.end());
+        for (int rr = 0; rr < nr; ++rr)
+            for (int l = 0; l < 64; ++l) t.pn_code.push_back(rr < (int)lanes[l].size() ? lanes[l][rr] : null_code);
     }
     t.pn_ptr[cnt.size() - 1] = (int64_t)t.pn_code.size();
     // the pn kernel reads the codes through a buffer resource with 32-bit byte offsets

@@ -23,7 +23,9 @@
 //            32-column source tiles, keeps its R tile in LDS, and the neutron
 //            one-body jumps whose source lies in the tile (pre-grouped by
 //            tile, read coalesced) add phase_l R[B_l, jn_l] into the wave's
-//            output row held in LDS.
+//            output row held in LDS. Within a tile every destination column
+//            belongs to one lane, which sums its entries in a register and
+//            updates the output row once.
 //            This is the proton-first grouping of sum_{A,B} V_AB P_A X N_B^T:
 //            the contraction over B is dense, so the matrix cores execute
 //            about 6.5 times the useful multiply-adds of the pn part. Adds to
@@ -191,12 +193,13 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
 
 // Contraction and gather of one fetched tile; cv holds the class's C operand.
 // PRIV: yl is this wave's private output row, updated by plain LDS
-// read-modify-write (the lanes of one round have distinct destinations and a
-// wave's LDS operations complete in order); otherwise yl is the workgroup's
-// shared row, updated with LDS atomics.
+// read-modify-write (no two lanes of a tile share a destination and a wave's
+// LDS operations complete in order); otherwise yl is the workgroup's shared
+// row, updated with LDS atomics (one per entry, never two on one address in
+// an instruction).
 template <typename T, bool PRIV, int NBT, int KST>
 __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[NBT][KST],
-                                        __amdgpu_buffer_rsrc_t cres, uint32_t null_code, int lane,
+                                        __amdgpu_buffer_rsrc_t cres, uint32_t null_code, int spare, int lane,
                                         T *__restrict__ R, T *__restrict__ yl) {
     typedef typename Mma<T>::acc_t acc_t;
     if (b.e0 == b.e1) return;   // uniform: no neutron jump leaves this tile
@@ -218,15 +221,56 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
     // a wave's LDS operations complete in issue order: the gather below
     // sees the stores above without a workgroup barrier
     __builtin_amdgcn_wave_barrier();
-    // Each round of 64 entries has distinct destinations, so the lanes of one
-    // LDS instruction never hit the same address; the list of a tile is a
-    // whole number of rounds, so rounds are skipped per wave, not per lane.
+    // The list of a tile is a whole number of 64-entry rounds, so rounds are
+    // skipped per wave, not per lane.
     const int ne = b.e1 - b.e0;
+    if constexpr (PRIV) {
+        // Each lane owns its destinations for the whole tile: it sums a
+        // destination's entries in `run` and adds the sum to the output row
+        // at the flagged last entry. No two lanes share a destination within
+        // the tile and a lane flushes each of its destinations once, so the
+        // output-row reads of a pair of rounds go out before either write;
+        // a round without a flush reads and writes the lane's own scratch
+        // word past the row.
+        constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
+        const uint32_t own = (uint32_t)(spare + lane);
+        T run = 0;
+        // rounds in pairs: both R reads, then both output-row reads, then
+        // both writes (a round past the list's end takes the null code)
 #pragma unroll
-    for (int i = 0; i < kPnRounds; ++i)
-        if (64 * i < ne) pn_add<T, PRIV>(yl, R, b.cr[i], null_code);
-    for (int i = 64 * kPnRounds; i < ne; i += 64)
-        pn_add<T, PRIV>(yl, R, buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u), null_code);
+        for (int i = 0; i < kPnRounds; i += 2) {
+            if (64 * i < ne) {
+                const uint32_t c0 = b.cr[i];
+                const uint32_t c1 = 64 * (i + 1) < ne ? b.cr[i + 1] : null_code;
+                const T v0 = signed_by(R[c0 & kElem], c0);
+                const T v1 = signed_by(R[c1 & kElem], c1);
+                const uint32_t a0 = (c0 & kPnFlush) ? (c0 >> kPnRBits) & kDst : own;
+                const uint32_t a1 = (c1 & kPnFlush) ? (c1 >> kPnRBits) & kDst : own;
+                const T s0 = run + v0;
+                const T r1 = (c0 & kPnFlush) ? T(0) : s0;
+                const T s1 = r1 + v1;
+                run = (c1 & kPnFlush) ? T(0) : s1;
+                const T y0 = yl[a0];
+                const T y1 = yl[a1];
+                yl[a0] = y0 + s0;
+                yl[a1] = y1 + s1;
+            }
+        }
+        for (int i = 64 * kPnRounds; i < ne; i += 64) {
+            const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u);
+            run += signed_by(R[c & kElem], c);
+            if (c & kPnFlush) {
+                yl[(c >> kPnRBits) & kDst] += run;
+                run = 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPnRounds; ++i)
+            if (64 * i < ne) pn_add<T, PRIV>(yl, R, b.cr[i], null_code);
+        for (int i = 64 * kPnRounds; i < ne; i += 64)
+            pn_add<T, PRIV>(yl, R, buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u), null_code);
+    }
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -271,13 +315,13 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
         pn_fetch<T, KST, NB>(B, 1, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
         for (int j = 0;; j += 3) {
             pn_fetch<T, KST, NB>(C, j + 2, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
+            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, pc.spare, lane, R, yl);
             if (wid + W * (j + 1) >= ntiles) break;
             pn_fetch<T, KST, NB>(A, j + 3, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
+            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, pc.spare, lane, R, yl);
             if (wid + W * (j + 2) >= ntiles) break;
             pn_fetch<T, KST, NB>(B, j + 4, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(C, cv, cres, pc.null_code, lane, R, yl);
+            pn_work<T, PRIV, NBT, KST>(C, cv, cres, pc.null_code, pc.spare, lane, R, yl);
             if (wid + W * (j + 3) >= ntiles) break;
         }
     } else {
@@ -286,10 +330,10 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
         pn_fetch<T, KST, NB>(A, 0, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
         for (int j = 0;; j += 2) {
             pn_fetch<T, KST, NB>(B, j + 1, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, lane, R, yl);
+            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, pc.spare, lane, R, yl);
             if (wid + W * (j + 1) >= ntiles) break;
             pn_fetch<T, KST, NB>(A, j + 2, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, lane, R, yl);
+            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, pc.spare, lane, R, yl);
             if (wid + W * (j + 2) >= ntiles) break;
         }
     }
@@ -350,7 +394,8 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
     const __amdgpu_buffer_rsrc_t cres =
         __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn_code, (short)0, (int)(TT.n_pn_code * 4), kBufFlags);
     T *R = Rw[wid];
-    const int ystride = TT.max_nn + 1;   // one padding column per row
+    // one padding column per row, and with private rows 64 scratch words (one per lane)
+    const int ystride = TT.max_nn + 1 + (PRIV ? 64 : 0);
     T *yl = PRIV ? yall + wid * ystride : yall;
     for (int w = 0; w < (PRIV ? kPnWaves : 1); ++w)
         for (int c = tid; c < nn; c += kPnThreads) yall[w * ystride + c] = 0;
@@ -360,6 +405,7 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
     pc.ob_code = P.p.ob_code;
     pc.ob_base = TT.p_ob_base;
     pc.null_code = TT.pn_null;
+    pc.spare = TT.max_nn + 1;
     for (int q = 0; q < nq; ++q) {
         const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q], a1 = P.p.ob_ptr[(int64_t)ip * nq + q + 1];
         if (a0 == a1) continue;   // uniform across the workgroup
@@ -398,7 +444,7 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
 // atomics are far slower than a read and a write
 template <typename T, int NB>
 void launch_pn_nb(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_t st) {
-    const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1) * sizeof(T);
+    const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1 + 64) * sizeof(T);
     const dim3 grid = NB == 1 ? dim3(d.p.n_sd) : dim3((unsigned)((d.p.n_sd + 7) / 8 * 8 * NB));
     bool priv = false;
     if constexpr (sizeof(T) == 4) {

@@ -114,9 +114,10 @@ __device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, un
 
 constexpr int kPnRounds = 8;   // gather rounds of a tile loaded with the tile's x values
 
-// One gather entry: yl[dst] += phase * R[element] (code layout as in
-// pn_code). With private rows the padding code is applied too (it adds to
-// the padding column); with the shared row it is skipped.
+// One gather entry on its own: yl[dst] += phase * R[element] (code layout as
+// in pn_code; the flush bit is not used). With private rows the padding code
+// is applied too (it adds to the padding column); with the shared row it is
+// skipped.
 template <typename T, bool PRIV>
 __device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__ R, uint32_t c, uint32_t null_code) {
     const T v = signed_by(R[c & ((1u << kPnRBits) - 1u)], c);
@@ -147,6 +148,7 @@ struct PnClass {
     const int64_t *ob_base;   // their source rows' offsets in x
     int a0, kp, nB;
     uint32_t null_code;       // padding entry of the gather lists
+    int spare;                // first per-lane scratch word of a private output row
 };
 
 // Workgroups are dealt to the 8 XCDs in turn (slot b runs on XCD b % 8). A
