@@ -178,20 +178,64 @@ void build_tiled_tables(fotci_ham *h) {
         });
         for (size_t i : by_src) order[fill[slot(rec[i])]++] = i;
     }
-    // Pack each slot into rounds of 64 lanes in which every destination
-    // column is owned by one lane: its entries occupy consecutive rounds of
-    // that lane and the last one carries the flush bit, so the kernel sums
-    // them in a register and touches the output row once per destination
-    // and tile; no two lanes of a tile ever share a destination. Destinations
-    // go to the least-loaded lane, most entries first; rounds are padded to
-    // the busiest lane with the null code (R element 0, the spare column,
-    // no flush).
+    // Pack each slot into rounds of 64 lanes. A destination column's entries
+    // go to one lane in consecutive rounds (a chunk); the chunk's last entry
+    // carries the flush bit, so the kernel sums the chunk in a register and
+    // touches the output row once for it. The kernel works through rounds in
+    // pairs, reading the output row for both rounds before writing either,
+    // so two chunks of one destination must flush in different pairs; apart
+    // from that a destination may be split over several lanes, which keeps
+    // the rounds near ceil(entries / 64) even when one column receives many
+    // entries. Destinations are placed most entries first, each chunk in the
+    // lane with the most free rounds, for the smallest round count that
+    // succeeds; unused slots get the null code (R element 0, the spare
+    // column, no flush).
     const uint32_t null_code = (uint32_t)t.max_nn << kPnRBits;
     t.pn_ptr.assign(cnt.size(), 0);
     t.pn_code.clear();
     std::vector<std::pair<uint32_t, std::vector<uint32_t>>> bydst;
     std::vector<std::vector<uint32_t>> lanes(64);
-    std::vector<int> load(64);
+    std::vector<int> lane_order(64);
+    std::vector<char> used_pairs;
+    auto pack = [&](int nr) -> bool {
+        for (auto &l : lanes) l.clear();
+        if ((int)used_pairs.size() < (nr + 1) / 2) used_pairs.resize((nr + 1) / 2);
+        for (auto &dl : bydst) {
+            const auto &e = dl.second;
+            size_t done = 0;
+            std::fill(used_pairs.begin(), used_pairs.begin() + (nr + 1) / 2, 0);   // pairs where a chunk flushes
+            while (done < e.size()) {
+                // a chunk in lane l: as many entries as fit whose flush falls in a pair not yet used
+                auto try_lane = [&](int l) -> bool {
+                    const int ptr = (int)lanes[l].size();
+                    int size = std::min<int>((int)(e.size() - done), nr - ptr);
+                    while (size > 0 && used_pairs[(ptr + size - 1) / 2]) --size;
+                    if (size <= 0) return false;
+                    used_pairs[(ptr + size - 1) / 2] = 1;
+                    for (int i = 0; i < size; ++i) lanes[l].push_back(e[done + i] | (i + 1 == size ? kPnFlush : 0u));
+                    done += (size_t)size;
+                    return true;
+                };
+                // the emptiest lane first; the others by free rounds only if it cannot take a chunk
+                int best = 0;
+                for (int l = 1; l < 64; ++l)
+                    if (lanes[l].size() < lanes[best].size()) best = l;
+                bool placed = try_lane(best);
+                if (!placed) {
+                    for (int l = 0; l < 64; ++l) lane_order[l] = l;
+                    std::stable_sort(lane_order.begin(), lane_order.end(),
+                                     [&](int x, int y) { return lanes[x].size() < lanes[y].size(); });
+                    for (int l : lane_order)
+                        if (l != best && try_lane(l)) {
+                            placed = true;
+                            break;
+                        }
+                }
+                if (!placed) return false;
+            }
+        }
+        return true;
+    };
     for (size_t sl = 0; sl + 1 < cnt.size(); ++sl) {
         t.pn_ptr[sl] = (int64_t)t.pn_code.size();
         if (cnt[sl] == cnt[sl + 1]) continue;
@@ -216,15 +260,9 @@ void build_tiled_tables(fotci_ham *h) {
             if (x.second.size() != y.second.size()) return x.second.size() > y.second.size();
             return x.first < y.first;
         });
-        for (auto &l : lanes) l.clear();
-        std::fill(load.begin(), load.end(), 0);
-        for (auto &dl : bydst) {
-            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            for (size_t i = 0; i < dl.second.size(); ++i)
-                lanes[l].push_back(dl.second[i] | (i + 1 == dl.second.size() ? kPnFlush : 0u));
-            load[l] += (int)dl.second.size();
-        }
-        const int nr = *std::max_element(load.begin(), load.end());
+        const int64_t n = cnt[sl + 1] - cnt[sl];
+        int nr = (int)std::max<int64_t>(1, (n + 63) / 64);
+        while (!pack(nr)) ++nr;
         for (int rr = 0; rr < nr; ++rr)
             for (int l = 0; l < 64; ++l) t.pn_code.push_back(rr < (int)lanes[l].size() ? lanes[l][rr] : null_code);
     }
