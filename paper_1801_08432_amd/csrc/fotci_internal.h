@@ -134,6 +134,18 @@ struct DevHam {
     DevSpecies p, n;
 };
 
+// One ELL entry of the nn / pp kernels: the local source index and the merged
+// matrix element, read with a single 8- or 12-byte load (the float64 value as
+// two 32-bit words, low first).
+struct alignas(8) EllE32 {
+    int32_t src;
+    float v;
+};
+struct alignas(4) EllE64 {
+    int32_t src;
+    uint32_t v_lo, v_hi;
+};
+
 // Extra device tables of the tiled kernels (indexed by basis sector s; each
 // basis sector owns one proton and one neutron species sector).
 struct DevTiled {
@@ -145,15 +157,16 @@ struct DevTiled {
     const int32_t *nn_ell_E;     // [n_sectors]
     const int32_t *nn_ell_src;   // local source column
     const int32_t *nn_ell_ent;   // merged neutron entry index, -1 for padding
-    double *nn_ell_v64;
-    float *nn_ell_v32;
+    // the entries the kernels walk, source and value side by side (one load each)
+    EllE32 *nn_ell_e32;
+    EllE64 *nn_ell_e64;
     // pp: per sector an ELL table over destination proton rows (e*np_s + r)
     const int64_t *pp_ell_base;
     const int32_t *pp_ell_E;
     const int32_t *pp_ell_src;   // local source row
     const int32_t *pp_ell_ent;
-    double *pp_ell_v64;
-    float *pp_ell_v32;
+    EllE32 *pp_ell_e32;
+    EllE64 *pp_ell_e64;
     int64_t nn_ell_len, pp_ell_len;
     // nn / pp workgroup tiles
     const int32_t *rt_sec, *rt_r0;   // [n_rtiles] row tiles (nn kernel)

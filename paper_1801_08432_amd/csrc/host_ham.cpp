@@ -446,14 +446,14 @@ std::vector<Item> items(fotci_ham *h) {
     add(tt.nn_ell_E.data(), tt.nn_ell_E.size() * 4, &dt.nn_ell_E);
     add(tt.nn_ell_src.data(), tt.nn_ell_src.size() * 4, &dt.nn_ell_src);
     add(tt.nn_ell_ent.data(), tt.nn_ell_ent.size() * 4, &dt.nn_ell_ent);
-    add(nullptr, tt.nn_ell_src.size() * 8, &dt.nn_ell_v64);
-    add(nullptr, tt.nn_ell_src.size() * 4, &dt.nn_ell_v32);
+    add(nullptr, tt.nn_ell_src.size() * sizeof(EllE64), &dt.nn_ell_e64);
+    add(nullptr, tt.nn_ell_src.size() * sizeof(EllE32), &dt.nn_ell_e32);
     add(tt.pp_ell_base.data(), tt.pp_ell_base.size() * 8, &dt.pp_ell_base);
     add(tt.pp_ell_E.data(), tt.pp_ell_E.size() * 4, &dt.pp_ell_E);
     add(tt.pp_ell_src.data(), tt.pp_ell_src.size() * 4, &dt.pp_ell_src);
     add(tt.pp_ell_ent.data(), tt.pp_ell_ent.size() * 4, &dt.pp_ell_ent);
-    add(nullptr, tt.pp_ell_src.size() * 8, &dt.pp_ell_v64);
-    add(nullptr, tt.pp_ell_src.size() * 4, &dt.pp_ell_v32);
+    add(nullptr, tt.pp_ell_src.size() * sizeof(EllE64), &dt.pp_ell_e64);
+    add(nullptr, tt.pp_ell_src.size() * sizeof(EllE32), &dt.pp_ell_e32);
     add(tt.rt_sec.data(), tt.rt_sec.size() * 4, &dt.rt_sec);
     add(tt.rt_r0.data(), tt.rt_r0.size() * 4, &dt.rt_r0);
     add(tt.ct_sec.data(), tt.ct_sec.size() * 4, &dt.ct_sec);

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
     const int64_t off = P.sec_off[s];
     const int E = TT.nn_ell_E[s];
     const int64_t eb = TT.nn_ell_base[s];
-    const T *ev = TabT<T>::nn_ell(TT);
+    const auto *ev = TabT<T>::nn_ell(TT);
     const T *dpa = TabT<T>::diag(P.p);
     const T *dn = TabT<T>::diag(P.n);
     const int rend = min(r0t + kTile, np);
@@ -87,9 +87,9 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
             }
 #pragma unroll 8
             for (int e = 0; e < E; ++e) {
-                const int64_t k = eb + (int64_t)e * nn + c;
-                const int src = TT.nn_ell_src[k];
-                const T val = ev[k];
+                const auto ent = ell_load(ev, eb + (int64_t)e * nn + c);
+                const int src = ent.src;
+                const T val = ent.v;
                 const RowT *xr = Xl + src * RT;
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *_
     const int E = TT.pp_ell_E[s];
     if (E == 0) return;
     const int64_t eb = TT.pp_ell_base[s];
-    const T *ev = TabT<T>::pp_ell(TT);
+    const auto *ev = TabT<T>::pp_ell(TT);
     const int cend = min(c0t + kTile, nn);
     for (int c0 = c0t; c0 < cend; c0 += CT) {
         const int nc = min(CT, cend - c0);
@@ -147,9 +147,9 @@ __global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *_
                 for (int v = 0; v < NB; ++v) acc[c][v] = 0;
 #pragma unroll 8
             for (int e = 0; e < E; ++e) {
-                const int64_t k = eb + (int64_t)e * np + r;
-                const int src = TT.pp_ell_src[k];
-                const T val = ev[k];
+                const auto ent = ell_load(ev, eb + (int64_t)e * np + r);
+                const int src = ent.src;
+                const T val = ent.v;
                 const RowT *xr = Xl + src * CT;
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {

@@ -39,14 +39,16 @@ namespace fotci {
 
 namespace {
 
-__global__ __launch_bounds__(kT) void k_ell_values(const int32_t *__restrict__ ent, const double *__restrict__ off,
-                                                   double *__restrict__ v64, float *__restrict__ v32, int64_t n) {
+__global__ __launch_bounds__(kT) void k_ell_values(const int32_t *__restrict__ src, const int32_t *__restrict__ ent,
+                                                   const double *__restrict__ off, EllE64 *__restrict__ e64,
+                                                   EllE32 *__restrict__ e32, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= n) return;
     const int e = ent[i];
     const double v = e >= 0 ? off[e] : 0.0;
-    v64[i] = v;
-    v32[i] = (float)v;
+    const uint64_t bits = __double_as_longlong(v);
+    e64[i] = EllE64{src[i], (uint32_t)bits, (uint32_t)(bits >> 32)};
+    e32[i] = EllE32{src[i], (float)v};
 }
 
 // ------------------------------------------------------------ diagonal + nn
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
     const int64_t off = P.sec_off[s];
     const int E = TT.nn_ell_E[s];
     const int64_t eb = TT.nn_ell_base[s];
-    const T *ev = TabT<T>::nn_ell(TT);
+    const auto *ev = TabT<T>::nn_ell(TT);
     const T *dpa = TabT<T>::diag(P.p);
     const T *dn = TabT<T>::diag(P.n);
     const int rend = min(r0t + kTile, np);
@@ -87,9 +89,9 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
             for (int r = 0; r < RT; ++r) acc[r] = (dp[r] + dnc) * Xl[c * RT + r];
 #pragma unroll 8
             for (int e = 0; e < E; ++e) {
-                const int64_t k = eb + (int64_t)e * nn + c;
-                const int src = TT.nn_ell_src[k];
-                const T v = ev[k];
+                const auto ent = ell_load(ev, eb + (int64_t)e * nn + c);
+                const int src = ent.src;
+                const T v = ent.v;
                 const T *xr = Xl + src * RT;
 #pragma unroll
                 for (int r = 0; r < RT; ++r) acc[r] += v * xr[r];
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
     const int E = TT.pp_ell_E[s];
     if (E == 0) return;
     const int64_t eb = TT.pp_ell_base[s];
-    const T *ev = TabT<T>::pp_ell(TT);
+    const auto *ev = TabT<T>::pp_ell(TT);
     const int cend = min(c0t + kTile, nn);
     for (int c0 = c0t; c0 < cend; c0 += CT) {
         const int nc = min(CT, cend - c0);
@@ -134,9 +136,9 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
             for (int c = 0; c < CT; ++c) acc[c] = 0;
 #pragma unroll 8
             for (int e = 0; e < E; ++e) {
-                const int64_t k = eb + (int64_t)e * np + r;
-                const int src = TT.pp_ell_src[k];
-                const T v = ev[k];
+                const auto ent = ell_load(ev, eb + (int64_t)e * np + r);
+                const int src = ent.src;
+                const T v = ent.v;
                 const T *xr = Xl + src * CT;
 #pragma unroll
                 for (int c = 0; c < CT; ++c) acc[c] += v * xr[c];
@@ -488,10 +490,12 @@ void launch_materialize_tiled(const DevHam &d, const DevTiled &t, void *stream) 
     hipStream_t st = (hipStream_t)stream;
     if (t.nn_ell_len > 0)
         hipLaunchKernelGGL(k_ell_values, dim3((unsigned)((t.nn_ell_len + kT - 1) / kT)), dim3(kT), 0, st,
-                           t.nn_ell_ent, (const double *)d.n.off_val64, t.nn_ell_v64, t.nn_ell_v32, t.nn_ell_len);
+                           t.nn_ell_src, t.nn_ell_ent, (const double *)d.n.off_val64, t.nn_ell_e64, t.nn_ell_e32,
+                           t.nn_ell_len);
     if (t.pp_ell_len > 0)
         hipLaunchKernelGGL(k_ell_values, dim3((unsigned)((t.pp_ell_len + kT - 1) / kT)), dim3(kT), 0, st,
-                           t.pp_ell_ent, (const double *)d.p.off_val64, t.pp_ell_v64, t.pp_ell_v32, t.pp_ell_len);
+                           t.pp_ell_src, t.pp_ell_ent, (const double *)d.p.off_val64, t.pp_ell_e64, t.pp_ell_e32,
+                           t.pp_ell_len);
     hip_check(hipGetLastError(), "materialize launch");
 }
 

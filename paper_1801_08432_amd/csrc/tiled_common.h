@@ -50,16 +50,34 @@ template <>
 struct TabT<double> {
     static __device__ __forceinline__ const double *diag(const DevSpecies &s) { return s.d64; }
     static __device__ __forceinline__ const double *vq(const DevHam &h) { return h.vq64; }
-    static __device__ __forceinline__ const double *nn_ell(const DevTiled &t) { return t.nn_ell_v64; }
-    static __device__ __forceinline__ const double *pp_ell(const DevTiled &t) { return t.pp_ell_v64; }
+    static __device__ __forceinline__ const EllE64 *nn_ell(const DevTiled &t) { return t.nn_ell_e64; }
+    static __device__ __forceinline__ const EllE64 *pp_ell(const DevTiled &t) { return t.pp_ell_e64; }
 };
 template <>
 struct TabT<float> {
     static __device__ __forceinline__ const float *diag(const DevSpecies &s) { return s.d32; }
     static __device__ __forceinline__ const float *vq(const DevHam &h) { return h.vq32; }
-    static __device__ __forceinline__ const float *nn_ell(const DevTiled &t) { return t.nn_ell_v32; }
-    static __device__ __forceinline__ const float *pp_ell(const DevTiled &t) { return t.pp_ell_v32; }
+    static __device__ __forceinline__ const EllE32 *nn_ell(const DevTiled &t) { return t.nn_ell_e32; }
+    static __device__ __forceinline__ const EllE32 *pp_ell(const DevTiled &t) { return t.pp_ell_e32; }
 };
+
+// One ELL entry of the nn / pp kernels as one vector load.
+struct EllVal32 {
+    int src;
+    float v;
+};
+struct EllVal64 {
+    int src;
+    double v;
+};
+__device__ __forceinline__ EllVal32 ell_load(const EllE32 *__restrict__ e, int64_t k) {
+    const uint2 q = *reinterpret_cast<const uint2 *>(e + k);
+    return EllVal32{(int)q.x, __uint_as_float(q.y)};
+}
+__device__ __forceinline__ EllVal64 ell_load(const EllE64 *__restrict__ e, int64_t k) {
+    const uint3 q = *reinterpret_cast<const uint3 *>(e + k);
+    return EllVal64{(int)q.x, __hiloint2double((int)q.z, (int)q.y)};
+}
 
 constexpr int kPnThreads = 64 * kPnWaves;
 constexpr int kPnHalves = kPnTile / 16;   // 16-column matrix-core blocks per tile
