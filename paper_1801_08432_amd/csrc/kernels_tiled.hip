@@ -195,10 +195,9 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
 
 // Contraction and gather of one fetched tile; cv holds the class's C operand.
 // PRIV: yl is this wave's private output row, updated by plain LDS
-// read-modify-write (no two lanes of a tile share a destination and a wave's
-// LDS operations complete in order); otherwise yl is the workgroup's shared
-// row, updated with LDS atomics (one per entry, never two on one address in
-// an instruction).
+// read-modify-write (two chunks of one destination never flush in one pair of
+// rounds and a wave's LDS operations complete in order); otherwise yl is the
+// workgroup's shared row, updated with one LDS atomic per chunk.
 template <typename T, bool PRIV, int NBT, int KST>
 __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[NBT][KST],
                                         __amdgpu_buffer_rsrc_t cres, uint32_t null_code, int spare, int lane,
@@ -227,13 +226,12 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
     // skipped per wave, not per lane.
     const int ne = b.e1 - b.e0;
     if constexpr (PRIV) {
-        // Each lane owns its destinations for the whole tile: it sums a
-        // destination's entries in `run` and adds the sum to the output row
-        // at the flagged last entry. No two lanes share a destination within
-        // the tile and a lane flushes each of its destinations once, so the
-        // output-row reads of a pair of rounds go out before either write;
-        // a round without a flush reads and writes the lane's own scratch
-        // word past the row.
+        // A chunk of one destination's entries sits in consecutive rounds of
+        // one lane: the lane sums it in `run` and adds the sum to the output
+        // row at the chunk's flagged last entry. Two chunks of one destination
+        // never flush in the same pair of rounds, so the output-row reads of a
+        // pair go out before either write; a round without a flush reads and
+        // writes the lane's own scratch word past the row.
         constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
         const uint32_t own = (uint32_t)(spare + lane);
         T run = 0;
@@ -267,11 +265,28 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
             }
         }
     } else {
+        // shared row: the lane sums its chunk in a register and adds it with
+        // one LDS atomic at the chunk's flagged last entry
+        constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
+        T run = 0;
 #pragma unroll
         for (int i = 0; i < kPnRounds; ++i)
-            if (64 * i < ne) pn_add<T, PRIV>(yl, R, b.cr[i], null_code);
-        for (int i = 64 * kPnRounds; i < ne; i += 64)
-            pn_add<T, PRIV>(yl, R, buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u), null_code);
+            if (64 * i < ne) {
+                const uint32_t c = b.cr[i];
+                run += signed_by(R[c & kElem], c);
+                if (c & kPnFlush) {
+                    atomicAdd(&yl[(c >> kPnRBits) & kDst], run);
+                    run = 0;
+                }
+            }
+        for (int i = 64 * kPnRounds; i < ne; i += 64) {
+            const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u);
+            run += signed_by(R[c & kElem], c);
+            if (c & kPnFlush) {
+                atomicAdd(&yl[(c >> kPnRBits) & kDst], run);
+                run = 0;
+            }
+        }
     }
     __builtin_amdgcn_wave_barrier();
 }

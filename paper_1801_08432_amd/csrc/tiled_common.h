@@ -132,20 +132,6 @@ __device__ __forceinline__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, un
 
 constexpr int kPnRounds = 8;   // gather rounds of a tile loaded with the tile's x values
 
-// One gather entry on its own: yl[dst] += phase * R[element] (code layout as
-// in pn_code; the flush bit is not used). With private rows the padding code
-// is applied too (it adds to the padding column); with the shared row it is
-// skipped.
-template <typename T, bool PRIV>
-__device__ __forceinline__ void pn_add(T *__restrict__ yl, const T *__restrict__ R, uint32_t c, uint32_t null_code) {
-    const T v = signed_by(R[c & ((1u << kPnRBits) - 1u)], c);
-    const uint32_t d = (c >> kPnRBits) & ((1u << kPnDstBits) - 1u);
-    if (PRIV)
-        yl[d] += v;
-    else if (c != null_code)
-        atomicAdd(&yl[d], v);
-}
-
 // Gather-list ranges of the wave's tiles t = wid + W*(j0 + lane), one tile
 // per lane (ends past the last tile clamp to it), read once per 64 tiles so
 // that the tile loop picks them with readlane and issues no dependent load.
