@@ -7,8 +7,8 @@ LanczosEig  the lowest eigenvalues E_k(theta); backward gives
             dL/dtheta = sum_k dL/dE_k <psi_k| O_label |psi_k> (Hellmann-Feynman,
             valid for non-degenerate, converged states), the m-scheme analogue
             of the paper's diagonal two-body densities (Ch. 5, "Two-body
-            densities": the expectation value of a Hamiltonian with exactly one
-            matrix element set to one).
+            densities": the energy of a state under an interaction whose
+            elements are all zero except one, which is 1).
 
 theta is the interaction as five float64 tensors (eps_p, eps_n, v_pp, v_nn,
 v_pn) in the layout of fotci_set_interaction. The gradient of an array entry

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
             const int r = idx / nn, c = idx - r * nn;
             // rows past the tile's end load row nr-1 and store zero: no branch around the load
             const T v = xs[(int64_t)min(r, nr - 1) * nn + c];
-            Xl[c * RT + r] = r < nr ? v : T(0);
+            Xl[c * RT + (r ^ slab_swz<T, RT>(c))] = r < nr ? v : T(0);
         }
         T dp[RT];
 #pragma unroll
@@ -86,15 +86,16 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
             T acc[RT];
             const T dnc = dn[nf + c];
 #pragma unroll
-            for (int r = 0; r < RT; ++r) acc[r] = (dp[r] + dnc) * Xl[c * RT + r];
+            for (int r = 0; r < RT; ++r) acc[r] = (dp[r] + dnc) * Xl[c * RT + (r ^ slab_swz<T, RT>(c))];
 #pragma unroll 8
             for (int e = 0; e < E; ++e) {
                 const auto ent = ell_load(ev, eb + (int64_t)e * nn + c);
                 const int src = ent.src;
                 const T v = ent.v;
                 const T *xr = Xl + src * RT;
+                const int sw = slab_swz<T, RT>(src);
 #pragma unroll
-                for (int r = 0; r < RT; ++r) acc[r] += v * xr[r];
+                for (int r = 0; r < RT; ++r) acc[r] += v * xr[r ^ sw];
             }
 #pragma unroll
             for (int r = 0; r < RT; ++r)
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
         for (int idx = tid; idx < np * CT; idx += kT) {
             const int r = idx / CT, c = idx - r * CT;
             const T v = x[off + (int64_t)r * nn + c0 + min(c, nc - 1)];   // unconditional load
-            Xl[idx] = c < nc ? v : T(0);
+            Xl[r * CT + (c ^ slab_swz<T, CT>(r))] = c < nc ? v : T(0);
         }
         __syncthreads();
         for (int r = tid; r < np; r += kT) {
@@ -140,8 +141,9 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
                 const int src = ent.src;
                 const T v = ent.v;
                 const T *xr = Xl + src * CT;
+                const int sw = slab_swz<T, CT>(src);
 #pragma unroll
-                for (int c = 0; c < CT; ++c) acc[c] += v * xr[c];
+                for (int c = 0; c < CT; ++c) acc[c] += v * xr[c ^ sw];
             }
             T *yr = y + off + (int64_t)r * nn + c0;
 #pragma unroll

@@ -3,8 +3,9 @@
 //   dL/dx = H g, since H is real symmetric;
 //   dL/dV[label] = <g| O_label |x>: the label-wise transition density of the
 //   operator string that V[label] multiplies (the m-scheme analogue of the
-//   paper's two-body densities, Ch. 5 "Two-body densities": the expectation
-//   value of a Hamiltonian with exactly one matrix element set to one).
+//   paper's two-body densities, Ch. 5 "Two-body densities": a density is what
+//   <g|H|x> becomes when every interaction element but one is zero and that
+//   one is 1).
 // Each density is a sum over the same jumps apply_H uses:
 //   pp: phase * <g row dst, x row src> per proton two-body jump;
 //   nn: phase * <g column dst, x column src> per neutron two-body jump;

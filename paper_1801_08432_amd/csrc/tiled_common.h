@@ -177,6 +177,16 @@ inline unsigned pp_grid(int n_tiles, int g) { return (unsigned)((n_tiles + 8 * g
 
 // Largest tile (8, 4, 2 or 1 rows or columns) whose staged slab of max_len
 // elements of elem bytes each fits kLdsTile.
+// A staged line of 32 bytes (8 float or 4 double) is read as two 16-byte
+// halves; swapping the halves of every other run of 8 lines spreads the
+// lanes' random lines over all 16 LDS bank groups instead of the 8 even or
+// odd ones. Returns the element XOR mask for `line`.
+template <typename T, int L>
+__device__ __forceinline__ int slab_swz(int line) {
+    if constexpr (L * sizeof(T) == 32) return ((line >> 3) & 1) * (L / 2);
+    else return 0;
+}
+
 inline int pick_tile(int max_len, int elem) {
     int t = kTile;
     while (t > 1 && (int64_t)t * max_len * elem > kLdsTile) t >>= 1;
