@@ -25,6 +25,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+// Lanczos steps issued between two reads of alpha and beta by the host
+constexpr int kLazySteps = 16;
 constexpr int kRowsPerThread = 8;
 constexpr int kChunk = kThreads * kRowsPerThread;   // rows per block in the tall-skinny kernels
 constexpr int kMaxIter = 4096;
@@ -551,7 +553,7 @@ int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 // and small arrays.
 struct Layout {
     int64_t ld;   // basis leading dimension (elements): dim rounded up to 64
-    int64_t basis, scratch, y, w, partial, sq, scal, coef, S, ritz, hy, total;
+    int64_t basis, scratch, y, w, partial, sq, scal, coef, S, ritz, hy, hist, total;   // hist 0: none
 };
 
 Layout make_layout(int64_t dim, int es, int nvec, int nscr, int ncoef, int s_cols, int n_keep) {
@@ -581,6 +583,8 @@ Layout make_layout(int64_t dim, int es, int nvec, int nscr, int ncoef, int s_col
     off = a256(off + (int64_t)n_keep * dim * 8);
     L.hy = off;
     off = a256(off + dim * 8);
+    L.hist = off;
+    off = a256(off + (int64_t)std::max(ncoef, 1) * 16);
     L.total = off;
     return L;
 }
@@ -644,6 +648,7 @@ struct Lz {
     T *basis, *scratch, *y;
     double *w, *partial, *sq, *scal, *coef, *Sd, *ritz, *hy;   // scal: [0] alpha [1] beta [2] norm [3] theta
                                                               // [4] resid [5] norm before reorthogonalisation
+    double *hist;   // alpha_i, beta_i of the steps not yet read by the host (null in the block driver)
     int reorth;
     int second_passes = 0;
 
@@ -662,6 +667,7 @@ struct Lz {
         Sd = (double *)(work + L.S);
         ritz = evecs ? evecs : (double *)(work + L.ritz);
         hy = (double *)(work + L.hy);
+        hist = L.hist ? (double *)(work + L.hist) : nullptr;
     }
 
     T *vec(int i) const { return basis + (int64_t)i * ld; }
@@ -685,6 +691,33 @@ struct Lz {
     // classical Gram-Schmidt twice against v_0..v_i and beta = ||w||.
     // Returns alpha and beta on the host.
     void step(int i, bool three_term, const std::vector<double> &arrow, double &alpha, double &beta) {
+        issue(i, three_term, arrow);
+        double ab[2];
+        hip_check(hipMemcpyAsync(ab, scal, 16, hipMemcpyDeviceToHost, st), "lanczos copy");
+        hip_check(hipStreamSynchronize(st), "lanczos sync");
+        alpha = ab[0];
+        beta = ab[1];
+    }
+
+    // The step without the round trip: alpha_i and beta_i also go to hist[2i],
+    // hist[2i + 1], which the host reads for several steps at once (collect).
+    // The next vector is w / beta computed on the device, so the host only has
+    // to look at beta to stop at an invariant subspace, which it can do late:
+    // steps after a breakdown work on garbage that is then discarded.
+    void step_async(int i, bool three_term, const std::vector<double> &arrow) {
+        issue(i, three_term, arrow);
+        hip_check(hipMemcpyAsync(hist + 2 * i, scal, 16, hipMemcpyDeviceToDevice, st), "lanczos copy");
+    }
+
+    // alpha, beta of steps i0 <= i < i1 (issued with step_async) to the host
+    void collect(int i0, int i1, std::vector<double> &ab) {
+        ab.resize((size_t)2 * (i1 - i0));
+        hip_check(hipMemcpyAsync(ab.data(), hist + 2 * i0, (size_t)16 * (i1 - i0), hipMemcpyDeviceToHost, st),
+                  "lanczos copy");
+        hip_check(hipStreamSynchronize(st), "lanczos sync");
+    }
+
+    void issue(int i, bool three_term, const std::vector<double> &arrow) {
         T *vi = vec(i);
         launch_apply(h, mode, vi, y, st);
         dot_into((const T *)vi, (const T *)y, scal + 0, 0);
@@ -722,11 +755,6 @@ struct Lz {
             ++second_passes;
         }
         hip_check(hipGetLastError(), "lanczos launch");
-        double ab[2];
-        hip_check(hipMemcpyAsync(ab, scal, 16, hipMemcpyDeviceToHost, st), "lanczos copy");
-        hip_check(hipStreamSynchronize(st), "lanczos sync");
-        alpha = ab[0];
-        beta = ab[1];
     }
 
     // v_{i+1} = w / beta (beta in scal[1] from the last step)
@@ -794,19 +822,38 @@ void run(const fotci_ham *h, const fotci_lanczos_opts *o, const double *pivot, c
          double *resid, double *evecs, double *alpha_out, double *beta_out, hipStream_t st) {
     Lz<T> z(h, standard_layout(h, o), o->mode, o->reorth, work, evecs, st);
     z.start(pivot);
-    std::vector<double> al, be;
+    std::vector<double> al, be, ab;
     const std::vector<double> none;
     double tnorm = 0.0;
     int k = 0;
-    for (int i = 0; i < o->n_iter; ++i) {
-        double a, b;
-        z.step(i, true, none, a, b);
+    // false once the recurrence ends (last iteration or an invariant subspace)
+    auto accept = [&](int i, double a, double b) -> bool {
         al.push_back(a);
         be.push_back(b);
         k = i + 1;
         tnorm = std::max(tnorm, std::fabs(a) + b + (i > 0 ? be[i - 1] : 0.0));
-        if (i == o->n_iter - 1) break;
-        if (!(b > 1e-12 * tnorm)) break;   // invariant subspace reached
+        return i < o->n_iter - 1 && b > 1e-12 * tnorm;
+    };
+    // the DGKS test needs the host inside every step; otherwise alpha and
+    // beta are read every kLazySteps steps
+    const bool lazy = o->reorth != FOTCI_REORTH_DGKS;
+    int collected = 0;
+    for (int i = 0; i < o->n_iter; ++i) {
+        bool go = true;
+        if (lazy) {
+            z.step_async(i, true, none);
+            if (i == o->n_iter - 1 || (i + 1) % kLazySteps == 0) {
+                z.collect(collected, i + 1, ab);
+                for (int j = collected; j <= i && go; ++j)
+                    go = accept(j, ab[2 * (j - collected)], ab[2 * (j - collected) + 1]);
+                collected = i + 1;
+            }
+        } else {
+            double a, b;
+            z.step(i, true, none, a, b);
+            go = accept(i, a, b);
+        }
+        if (!go) break;
         z.store_next(i);
     }
     if (alpha_out)
@@ -838,7 +885,8 @@ void run_trlan(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivo
     z.start(pivot);
     std::vector<double> Tm((size_t)(kb + 1) * (kb + 1), 0.0);
     auto TT = [&](int i, int j) -> double & { return Tm[(size_t)i * (kb + 1) + j]; };
-    std::vector<double> arrow;
+    std::vector<double> arrow, ab;
+    const bool lazy = o->reorth != FOTCI_REORTH_DGKS;   // as in the standard driver
     int j0 = 0, restarts = 0, applies = 0, converged = 0;
     double tnorm = 0.0;
     std::vector<double> theta, Z;
@@ -846,20 +894,36 @@ void run_trlan(const fotci_ham *h, const fotci_trlan_opts *o, const double *pivo
     for (;;) {
         m = kb;
         bool breakdown = false;
-        for (int i = j0; i < kb; ++i) {
-            double a, b;
-            z.step(i, i > j0 || j0 == 0, i == j0 ? arrow : std::vector<double>(), a, b);
-            ++applies;
+        // false at an invariant subspace: the Ritz pairs so far are exact
+        auto accept = [&](int i, double a, double b) -> bool {
             TT(i, i) = a;
             TT(i, i + 1) = TT(i + 1, i) = b;
             double row = std::fabs(a) + b;
             for (int j = 0; j < i; ++j) row += std::fabs(TT(i, j));
             tnorm = std::max(tnorm, row);
-            if (!(b > 1e-12 * tnorm)) {   // invariant subspace: the Ritz pairs so far are exact
-                m = i + 1;
-                breakdown = true;
-                break;
+            if (b > 1e-12 * tnorm) return true;
+            m = i + 1;
+            breakdown = true;
+            return false;
+        };
+        int collected = j0;
+        for (int i = j0; i < kb; ++i) {
+            bool go = true;
+            ++applies;
+            if (lazy) {
+                z.step_async(i, i > j0 || j0 == 0, i == j0 ? arrow : std::vector<double>());
+                if (i == kb - 1 || (i + 1 - j0) % kLazySteps == 0) {
+                    z.collect(collected, i + 1, ab);
+                    for (int j = collected; j <= i && go; ++j)
+                        go = accept(j, ab[2 * (j - collected)], ab[2 * (j - collected) + 1]);
+                    collected = i + 1;
+                }
+            } else {
+                double a, b;
+                z.step(i, i > j0 || j0 == 0, i == j0 ? arrow : std::vector<double>(), a, b);
+                go = accept(i, a, b);
             }
+            if (!go) break;
             z.store_next(i);
         }
         std::vector<double> A((size_t)m * m);
