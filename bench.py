@@ -377,7 +377,7 @@ def main():
                                          "(x is reused from LDS and matrix-core operands), so its GB/s can "
                                          "exceed the HBM peak"))
     if dom == "k_pn":
-        pw = h.pn_work()
+        pw = h.pn_work(mode)
         mf = pw["mfma_instr"] * MFMA_FLOPS_PER_INSTR / t_dom / 1e12
         roof["mfma"] = dict(instr_per_launch=pw["mfma_instr"], executed_tflops=round(mf, 2),
                             executed_frac=round(mf / peak, 4),

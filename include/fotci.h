@@ -387,13 +387,18 @@ int fotci_lanczos_block(const fotci_ham *h, const fotci_block_lanczos_opts *o, c
 int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, int64_t *ops_pn,
                         int64_t *ops_diag);
 
-/* Work of the pn kernel of the tiled modes in one apply_H (host; no device
- * needed), counted from the tables the kernel walks: visited (destination
- * row, operator class, 32-column source tile) triples, 16x16x4 matrix-core
- * instructions, and gather slots including the padding of the 64-entry
- * rounds. Each output may be NULL. FOTCI_ESTATE when the tiled kernels are
- * not available for this basis. */
-int fotci_ham_pn_work(const fotci_ham *h, int64_t *tile_visits, int64_t *mfma_instr, int64_t *gather_slots);
+/* Work of the pn kernel that fotci_apply_H runs in `mode` (FOTCI_MODE_F32 or
+ * FOTCI_MODE_F64) in one apply_H (host; no device needed), counted from the
+ * tables the kernel walks: visited (destination row, operator class,
+ * 32-column source tile) triples, 16x16x4 matrix-core instructions, and
+ * gather slots including the padding of the 64-entry rounds. The float32
+ * kernel with a shared output row per pair of waves works through pairs of
+ * source tiles and contracts both tiles of a pair that has any jump; the
+ * others skip every tile without jumps. Each output may be NULL.
+ * FOTCI_EINVAL for another mode, FOTCI_ESTATE when the tiled kernels are not
+ * available for this basis. */
+int fotci_ham_pn_work(const fotci_ham *h, int32_t mode, int64_t *tile_visits, int64_t *mfma_instr,
+                      int64_t *gather_slots);
 
 /* Output-row policy of the float32 pn kernel (FOTCI_MODE_F32): 1 (default)
  * gives each wave a private LDS output row when they fit and adds with plain

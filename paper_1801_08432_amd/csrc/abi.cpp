@@ -55,7 +55,7 @@ extern "C" int fotci_ham_upload_impl(fotci_ham *, void *, int64_t, void *);
 extern "C" int fotci_ham_set_values_impl(fotci_ham *, const double *, const double *, const double *, const double *,
                                          const double *, void *);
 extern "C" int fotci_ham_op_counts_impl(const fotci_ham *, int64_t *, int64_t *, int64_t *, int64_t *);
-extern "C" int fotci_ham_pn_work_impl(const fotci_ham *, int64_t *, int64_t *, int64_t *);
+extern "C" int fotci_ham_pn_work_impl(const fotci_ham *, int32_t, int64_t *, int64_t *, int64_t *);
 extern "C" int fotci_decouple_tbme_impl(int32_t, const int32_t *, const int32_t *, int32_t, const fotci_tbme *, int32_t,
                                         const fotci_tbme *, int32_t, const fotci_tbme *, double *, double *, double *);
 extern "C" int fotci_ham_set_pn_private_rows_impl(fotci_ham *, int32_t);
@@ -308,8 +308,9 @@ int fotci_decouple_tbme(int32_t n_orbits, const int32_t *two_j, const int32_t *p
         [&] { return fotci_decouple_tbme_impl(n_orbits, two_j, parity, n_pp, pp, n_nn, nn, n_pn, pn, v_pp, v_nn, v_pn); });
 }
 
-int fotci_ham_pn_work(const fotci_ham *h, int64_t *tile_visits, int64_t *mfma_instr, int64_t *gather_slots) {
-    return guard([&] { return fotci_ham_pn_work_impl(h, tile_visits, mfma_instr, gather_slots); });
+int fotci_ham_pn_work(const fotci_ham *h, int32_t mode, int64_t *tile_visits, int64_t *mfma_instr,
+                      int64_t *gather_slots) {
+    return guard([&] { return fotci_ham_pn_work_impl(h, mode, tile_visits, mfma_instr, gather_slots); });
 }
 
 int fotci_ham_set_pn_private_rows(fotci_ham *h, int32_t enable) {

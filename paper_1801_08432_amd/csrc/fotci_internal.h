@@ -179,6 +179,15 @@ struct DevTiled {
                                  // there, `last` on the final one), padded with pn_null (R element 0, dst
                                  // col max_nn, not last)
     int64_t n_pn_code;           // entries of pn_code (a multiple of 64)
+    // the same jumps for the float32 one-vector kernel (k_pn2), one list per (destination sector, neutron
+    // class, pair of source tiles, destination-column parity): slot ((s*nq + qn)*n_s2 + pair)*2 + parity;
+    // codes as above with the R element (tile of the pair)*kPnTile*kPnRStride + col*kPnRStride + B in the
+    // low kPn2RBits bits and the destination column above them
+    const int32_t *pn2_ptr;      // [(n_sectors*nq)*n_s2*2 + 1]
+    const uint32_t *pn2_code;
+    int64_t n_pn2_code;
+    uint32_t pn2_null;           // padding code: R element 0, dst col max_nn, not last
+    int32_t n_s2;                // tile pairs per sector slot
     uint32_t pn_null;            // padding code
     int32_t n_t16;               // tiles per sector slot (ceil(max nn / kPnTile))
     int32_t kp_pad;              // max proton one-body jumps into a row per class, rounded up to 4
@@ -197,14 +206,19 @@ constexpr int kPnRStride = 68;
 constexpr int kPnRBits = 12;                // kPnTile * kPnRStride <= 1 << kPnRBits
 constexpr int kPnDstBits = 30 - kPnRBits;   // bit 30: last entry of its destination in its lane
 constexpr uint32_t kPnFlush = 1u << 30;
+constexpr int kPn2RBits = 13;               // 2 * kPnTile * kPnRStride <= 1 << kPn2RBits
+constexpr int kPn2DstBits = 30 - kPn2RBits;
 constexpr int kPnWaves = 2;                 // waves per pn workgroup
+// float32 pn: private output rows (and the one-vector kernel's shared row
+// with its two R tiles) are used when the wave-private rows would fit 32 KiB
+inline bool pn_private_rows_fit(int max_nn) { return (int64_t)kPnWaves * (max_nn + 1 + 64) * 4 <= 32768; }
 
 struct HostTiled {
     std::vector<int32_t> order, nn_ell_E, nn_ell_src, nn_ell_ent, pp_ell_E, pp_ell_src, pp_ell_ent;
     std::vector<int64_t> p_ob_base, nn_ell_base, pp_ell_base;
-    std::vector<int32_t> rt_sec, rt_r0, ct_sec, ct_c0, pn_ptr;
-    std::vector<uint32_t> pn_code;
-    int n_t16 = 0, kp_pad = 4, max_nn = 0, max_np = 0;
+    std::vector<int32_t> rt_sec, rt_r0, ct_sec, ct_c0, pn_ptr, pn2_ptr;
+    std::vector<uint32_t> pn_code, pn2_code;
+    int n_t16 = 0, n_s2 = 0, kp_pad = 4, max_nn = 0, max_np = 0;
     bool ok = false;
 };
 

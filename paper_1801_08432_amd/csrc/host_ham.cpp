@@ -157,118 +157,149 @@ void build_tiled_tables(fotci_ham *h) {
     std::vector<int32_t> nsec_to_bsec(b->n.sectors.size(), -1);
     for (int s = 0; s < S; ++s) nsec_to_bsec[b->sectors[s].n_sector] = s;
     const auto &rec = h->j->rec[FOTCI_JUMP_N1];
+    // Gather lists of the neutron one-body jumps, one list per slot (slot_of),
+    // each entry's code from code_of (sign, destination column << rbits, R
+    // element); see below for how a list is packed.
+    auto build_lists = [&](int64_t nslots, auto slot_of, auto code_of, int rbits, std::vector<int32_t> &ptr,
+                           std::vector<uint32_t> &codes) {
+        // group the jumps by slot, ordered inside a slot by (source, label)
+        std::vector<int64_t> cnt((size_t)nslots + 1, 0);
+        for (const auto &r : rec) cnt[slot_of(r) + 1]++;
+        for (size_t i = 0; i + 1 < cnt.size(); ++i) cnt[i + 1] += cnt[i];
+        std::vector<size_t> order(rec.size());
+        {
+            std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+            std::vector<size_t> by_src(rec.size());
+            for (size_t i = 0; i < rec.size(); ++i) by_src[i] = i;
+            std::stable_sort(by_src.begin(), by_src.end(), [&](size_t x, size_t y) {
+                if (rec[x].src != rec[y].src) return rec[x].src < rec[y].src;
+                return rec[x].label < rec[y].label;
+            });
+            for (size_t i : by_src) order[fill[slot_of(rec[i])]++] = i;
+        }
+        // Pack each slot into rounds of 64 lanes. A destination column's entries
+        // go to one lane in consecutive rounds (a chunk); the chunk's last entry
+        // carries the flush bit, so the kernel sums the chunk in a register and
+        // touches the output row once for it. The kernel works through rounds in
+        // pairs, reading the output row for both rounds before writing either,
+        // so two chunks of one destination must flush in different pairs; apart
+        // from that a destination may be split over several lanes, which keeps
+        // the rounds near ceil(entries / 64) even when one column receives many
+        // entries. Destinations are placed most entries first, each chunk in the
+        // lane with the most free rounds, for the smallest round count that
+        // succeeds; unused slots get the null code (R element 0, the spare
+        // column, no flush).
+        const uint32_t null_code = (uint32_t)t.max_nn << rbits;
+        ptr.assign(cnt.size(), 0);
+        codes.clear();
+        std::vector<std::pair<uint32_t, std::vector<uint32_t>>> bydst;
+        std::vector<std::vector<uint32_t>> lanes(64);
+        std::vector<int> lane_order(64);
+        std::vector<char> used_pairs;
+        auto pack = [&](int nr) -> bool {
+            for (auto &l : lanes) l.clear();
+            if ((int)used_pairs.size() < (nr + 1) / 2) used_pairs.resize((nr + 1) / 2);
+            for (auto &dl : bydst) {
+                const auto &e = dl.second;
+                size_t done = 0;
+                std::fill(used_pairs.begin(), used_pairs.begin() + (nr + 1) / 2, 0);   // pairs where a chunk flushes
+                while (done < e.size()) {
+                    // a chunk in lane l: as many entries as fit whose flush falls in a pair not yet used
+                    auto try_lane = [&](int l) -> bool {
+                        const int at = (int)lanes[l].size();
+                        int size = std::min<int>((int)(e.size() - done), nr - at);
+                        while (size > 0 && used_pairs[(at + size - 1) / 2]) --size;
+                        if (size <= 0) return false;
+                        used_pairs[(at + size - 1) / 2] = 1;
+                        for (int i = 0; i < size; ++i) lanes[l].push_back(e[done + i] | (i + 1 == size ? kPnFlush : 0u));
+                        done += (size_t)size;
+                        return true;
+                    };
+                    // the emptiest lane first; the others by free rounds only if it cannot take a chunk
+                    int best = 0;
+                    for (int l = 1; l < 64; ++l)
+                        if (lanes[l].size() < lanes[best].size()) best = l;
+                    bool placed = try_lane(best);
+                    if (!placed) {
+                        for (int l = 0; l < 64; ++l) lane_order[l] = l;
+                        std::stable_sort(lane_order.begin(), lane_order.end(),
+                                         [&](int x, int y) { return lanes[x].size() < lanes[y].size(); });
+                        for (int l : lane_order)
+                            if (l != best && try_lane(l)) {
+                                placed = true;
+                                break;
+                            }
+                    }
+                    if (!placed) return false;
+                }
+            }
+            return true;
+    };
+        for (size_t sl = 0; sl + 1 < cnt.size(); ++sl) {
+            ptr[sl] = (int32_t)codes.size();
+            if (cnt[sl] == cnt[sl + 1]) continue;
+            bydst.clear();
+            std::map<uint32_t, size_t> where;
+            for (int64_t k = cnt[sl]; k < cnt[sl + 1]; ++k) {
+                const auto &r = rec[order[k]];
+                const uint32_t dcol = (uint32_t)b->n.sd_local[r.dst];
+                const uint32_t code = code_of(r);
+                auto it = where.find(dcol);
+                if (it == where.end()) {
+                    where[dcol] = bydst.size();
+                    bydst.push_back({dcol, {code}});
+                } else {
+                    bydst[it->second].second.push_back(code);
+                }
+            }
+            std::stable_sort(bydst.begin(), bydst.end(), [](const auto &x, const auto &y) {
+                if (x.second.size() != y.second.size()) return x.second.size() > y.second.size();
+                return x.first < y.first;
+            });
+            const int64_t n = cnt[sl + 1] - cnt[sl];
+            int nr = (int)std::max<int64_t>(1, (n + 63) / 64);
+            while (!pack(nr)) ++nr;
+            for (int rr = 0; rr < nr; ++rr)
+                for (int l = 0; l < 64; ++l) codes.push_back(rr < (int)lanes[l].size() ? lanes[l][rr] : null_code);
+        }
+        ptr[cnt.size() - 1] = (int32_t)codes.size();
+    };
+    // one list per (sector, class, source tile) for the float64, block and
+    // adjoint kernels
     auto slot = [&](const JumpRec &r) -> int64_t {
         const int s = nsec_to_bsec[b->n.sd_sector[r.dst]];
         const int qn = cl.class_of[r.label];
         const int ch = b->n.sd_local[r.src] / kTL;
         return ((int64_t)s * nq + qn) * nch + ch;
     };
-    // group the jumps by slot, ordered inside a slot by (source, label)
-    std::vector<int64_t> cnt((size_t)S * nq * nch + 1, 0);
-    for (const auto &r : rec) cnt[slot(r) + 1]++;
-    for (size_t i = 0; i + 1 < cnt.size(); ++i) cnt[i + 1] += cnt[i];
-    std::vector<size_t> order(rec.size());
-    {
-        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-        std::vector<size_t> by_src(rec.size());
-        for (size_t i = 0; i < rec.size(); ++i) by_src[i] = i;
-        std::stable_sort(by_src.begin(), by_src.end(), [&](size_t x, size_t y) {
-            if (rec[x].src != rec[y].src) return rec[x].src < rec[y].src;
-            return rec[x].label < rec[y].label;
-        });
-        for (size_t i : by_src) order[fill[slot(rec[i])]++] = i;
-    }
-    // Pack each slot into rounds of 64 lanes. A destination column's entries
-    // go to one lane in consecutive rounds (a chunk); the chunk's last entry
-    // carries the flush bit, so the kernel sums the chunk in a register and
-    // touches the output row once for it. The kernel works through rounds in
-    // pairs, reading the output row for both rounds before writing either,
-    // so two chunks of one destination must flush in different pairs; apart
-    // from that a destination may be split over several lanes, which keeps
-    // the rounds near ceil(entries / 64) even when one column receives many
-    // entries. Destinations are placed most entries first, each chunk in the
-    // lane with the most free rounds, for the smallest round count that
-    // succeeds; unused slots get the null code (R element 0, the spare
-    // column, no flush).
-    const uint32_t null_code = (uint32_t)t.max_nn << kPnRBits;
-    t.pn_ptr.assign(cnt.size(), 0);
-    t.pn_code.clear();
-    std::vector<std::pair<uint32_t, std::vector<uint32_t>>> bydst;
-    std::vector<std::vector<uint32_t>> lanes(64);
-    std::vector<int> lane_order(64);
-    std::vector<char> used_pairs;
-    auto pack = [&](int nr) -> bool {
-        for (auto &l : lanes) l.clear();
-        if ((int)used_pairs.size() < (nr + 1) / 2) used_pairs.resize((nr + 1) / 2);
-        for (auto &dl : bydst) {
-            const auto &e = dl.second;
-            size_t done = 0;
-            std::fill(used_pairs.begin(), used_pairs.begin() + (nr + 1) / 2, 0);   // pairs where a chunk flushes
-            while (done < e.size()) {
-                // a chunk in lane l: as many entries as fit whose flush falls in a pair not yet used
-                auto try_lane = [&](int l) -> bool {
-                    const int ptr = (int)lanes[l].size();
-                    int size = std::min<int>((int)(e.size() - done), nr - ptr);
-                    while (size > 0 && used_pairs[(ptr + size - 1) / 2]) --size;
-                    if (size <= 0) return false;
-                    used_pairs[(ptr + size - 1) / 2] = 1;
-                    for (int i = 0; i < size; ++i) lanes[l].push_back(e[done + i] | (i + 1 == size ? kPnFlush : 0u));
-                    done += (size_t)size;
-                    return true;
-                };
-                // the emptiest lane first; the others by free rounds only if it cannot take a chunk
-                int best = 0;
-                for (int l = 1; l < 64; ++l)
-                    if (lanes[l].size() < lanes[best].size()) best = l;
-                bool placed = try_lane(best);
-                if (!placed) {
-                    for (int l = 0; l < 64; ++l) lane_order[l] = l;
-                    std::stable_sort(lane_order.begin(), lane_order.end(),
-                                     [&](int x, int y) { return lanes[x].size() < lanes[y].size(); });
-                    for (int l : lane_order)
-                        if (l != best && try_lane(l)) {
-                            placed = true;
-                            break;
-                        }
-                }
-                if (!placed) return false;
-            }
-        }
-        return true;
+    auto code1 = [&](const JumpRec &r) -> uint32_t {
+        const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kTL);
+        const uint32_t B = (uint32_t)cl.local_of[r.label];
+        return (r.phase < 0 ? 0x80000000u : 0u) | ((uint32_t)b->n.sd_local[r.dst] << kPnRBits) |
+               (so * (uint32_t)kPnRStride + B);
     };
-    for (size_t sl = 0; sl + 1 < cnt.size(); ++sl) {
-        t.pn_ptr[sl] = (int64_t)t.pn_code.size();
-        if (cnt[sl] == cnt[sl + 1]) continue;
-        bydst.clear();
-        std::map<uint32_t, size_t> where;
-        for (int64_t k = cnt[sl]; k < cnt[sl + 1]; ++k) {
-            const auto &r = rec[order[k]];
-            const uint32_t dcol = (uint32_t)b->n.sd_local[r.dst];
-            const uint32_t so = (uint32_t)(b->n.sd_local[r.src] % kTL);
-            const uint32_t B = (uint32_t)cl.local_of[r.label];
-            const uint32_t code =
-                (r.phase < 0 ? 0x80000000u : 0u) | (dcol << kPnRBits) | (so * (uint32_t)kPnRStride + B);
-            auto it = where.find(dcol);
-            if (it == where.end()) {
-                where[dcol] = bydst.size();
-                bydst.push_back({dcol, {code}});
-            } else {
-                bydst[it->second].second.push_back(code);
-            }
-        }
-        std::stable_sort(bydst.begin(), bydst.end(), [](const auto &x, const auto &y) {
-            if (x.second.size() != y.second.size()) return x.second.size() > y.second.size();
-            return x.first < y.first;
-        });
-        const int64_t n = cnt[sl + 1] - cnt[sl];
-        int nr = (int)std::max<int64_t>(1, (n + 63) / 64);
-        while (!pack(nr)) ++nr;
-        for (int rr = 0; rr < nr; ++rr)
-            for (int l = 0; l < 64; ++l) t.pn_code.push_back(rr < (int)lanes[l].size() ? lanes[l][rr] : null_code);
-    }
-    t.pn_ptr[cnt.size() - 1] = (int64_t)t.pn_code.size();
+    build_lists((int64_t)S * nq * nch, slot, code1, kPnRBits, t.pn_ptr, t.pn_code);
+    // the float32 one-vector kernel: a step is a pair of source tiles (one
+    // per wave), and each list holds the step's jumps into the destination
+    // columns of one parity, which one wave owns in the shared output row;
+    // the R element names the tile of the pair
+    t.n_s2 = (nch + 1) / 2;
+    auto slot2 = [&](const JumpRec &r) -> int64_t {
+        const int s = nsec_to_bsec[b->n.sd_sector[r.dst]];
+        const int qn = cl.class_of[r.label];
+        const int ch = b->n.sd_local[r.src] / kTL;
+        return (((int64_t)s * nq + qn) * t.n_s2 + ch / 2) * 2 + (b->n.sd_local[r.dst] & 1);
+    };
+    auto code2 = [&](const JumpRec &r) -> uint32_t {
+        const int sl = b->n.sd_local[r.src];
+        const uint32_t B = (uint32_t)cl.local_of[r.label];
+        return (r.phase < 0 ? 0x80000000u : 0u) | ((uint32_t)b->n.sd_local[r.dst] << kPn2RBits) |
+               ((uint32_t)((sl / kTL) & 1) * (uint32_t)(kPnTile * kPnRStride) + (uint32_t)(sl % kTL) * kPnRStride + B);
+    };
+    build_lists((int64_t)S * nq * t.n_s2 * 2, slot2, code2, kPn2RBits, t.pn2_ptr, t.pn2_code);
     // the pn kernel reads the codes through a buffer resource with 32-bit byte offsets
-    if ((int64_t)t.pn_code.size() * 4 > INT32_MAX) ok = false;
+    if ((int64_t)t.pn_code.size() * 4 > INT32_MAX || (int64_t)t.pn2_code.size() * 4 > INT32_MAX) ok = false;
+    if (t.max_nn + 1 + 128 > (1 << kPn2DstBits)) ok = false;
     t.ok = ok;
     const int npsd = (int)b->p.sd.size();
     t.order.resize(npsd);
@@ -437,6 +468,9 @@ std::vector<Item> items(fotci_ham *h) {
     dt.n_t16 = std::max(tt.n_t16, 1);
     dt.n_pn_code = (int64_t)tt.pn_code.size();
     dt.pn_null = (uint32_t)tt.max_nn << kPnRBits;
+    dt.n_pn2_code = (int64_t)tt.pn2_code.size();
+    dt.pn2_null = (uint32_t)tt.max_nn << kPn2RBits;
+    dt.n_s2 = std::max(tt.n_s2, 1);
     dt.kp_pad = tt.kp_pad;
     dt.max_nn = tt.max_nn;
     dt.max_np = tt.max_np;
@@ -460,6 +494,8 @@ std::vector<Item> items(fotci_ham *h) {
     add(tt.ct_c0.data(), tt.ct_c0.size() * 4, &dt.ct_c0);
     add(tt.pn_ptr.data(), tt.pn_ptr.size() * 4, &dt.pn_ptr);
     add(tt.pn_code.data(), tt.pn_code.size() * 4, &dt.pn_code);
+    add(tt.pn2_ptr.data(), tt.pn2_ptr.size() * 4, &dt.pn2_ptr);
+    add(tt.pn2_code.data(), tt.pn2_code.size() * 4, &dt.pn2_code);
     for (int sp = 0; sp < 2; ++sp) {
         HostSpeciesTables &t = sp == 0 ? h->tp : h->tn;
         DevSpecies &ds = sp == 0 ? d.p : d.n;
@@ -609,16 +645,20 @@ extern "C" int fotci_ham_op_counts_impl(const fotci_ham *h, int64_t *ops_pp, int
 
 // Work of the pn kernel in one apply_H, from the same tables and in the same
 // order the kernel visits them: per destination row and operator class with
-// proton jumps, every source tile whose gather list is not empty.
-extern "C" int fotci_ham_pn_work_impl(const fotci_ham *h, int64_t *tile_visits, int64_t *mfma_instr,
+// proton jumps, every source tile whose gather list is not empty (the
+// per-tile lists), or every existing tile of a tile pair whose two lists are
+// not both empty (the float32 one-vector kernel with its shared output row).
+extern "C" int fotci_ham_pn_work_impl(const fotci_ham *h, int32_t mode, int64_t *tile_visits, int64_t *mfma_instr,
                                       int64_t *gather_slots) {
-    if (!h) fail(FOTCI_EINVAL, "NULL handle");
+    if (!h || (mode != FOTCI_MODE_F32 && mode != FOTCI_MODE_F64)) fail(FOTCI_EINVAL, "bad argument");
     const HostTiled &t = h->tt;
     if (!t.ok) fail(FOTCI_ESTATE, "the tiled kernels are not available for this basis");
     const fotci_basis *b = h->j->b;
     const int nq = h->j->cls.nq;
-    const int ntl = std::max(t.n_t16, 1);
+    const int ntl = std::max(t.n_t16, 1), ns2 = std::max(t.n_s2, 1);
     const auto &tc = h->tc;
+    // the launch's choice of kernel for float32 vectors
+    const bool pairs = mode == FOTCI_MODE_F32 && h->pn_priv && pn_private_rows_fit(t.max_nn);
     int64_t visits = 0, mfma = 0, slots = 0;
     for (int ip = 0; ip < (int)b->p.sd.size(); ++ip) {
         const int s = tc.p_sector[ip];
@@ -630,13 +670,25 @@ extern "C" int fotci_ham_pn_work_impl(const fotci_ham *h, int64_t *tile_visits, 
             const int kst = (a1 - a0 + 3) / 4;
             const int nns = tc.sec_nn[tc.p_sector[h->tp.ob_src[a0]]];
             const int ntiles = (nns + kPnTile - 1) / kPnTile;
-            const int64_t base = ((int64_t)s * nq + qn) * ntl;
-            for (int tt = 0; tt < ntiles; ++tt) {
-                const int64_t ne = t.pn_ptr[base + tt + 1] - t.pn_ptr[base + tt];
-                if (ne == 0) continue;
-                visits += 1;
-                mfma += (int64_t)(kPnTile / 16) * nbt * kst;
-                slots += ne;
+            if (pairs) {
+                const int64_t base = ((int64_t)s * nq + qn) * ns2 * 2;
+                for (int st = 0; st < (ntiles + 1) / 2; ++st) {
+                    const int64_t ne = t.pn2_ptr[base + 2 * st + 2] - t.pn2_ptr[base + 2 * st];
+                    if (ne == 0) continue;
+                    const int nt = std::min(2, ntiles - 2 * st);
+                    visits += nt;
+                    mfma += (int64_t)nt * (kPnTile / 16) * nbt * kst;
+                    slots += ne;
+                }
+            } else {
+                const int64_t base = ((int64_t)s * nq + qn) * ntl;
+                for (int tt = 0; tt < ntiles; ++tt) {
+                    const int64_t ne = t.pn_ptr[base + tt + 1] - t.pn_ptr[base + tt];
+                    if (ne == 0) continue;
+                    visits += 1;
+                    mfma += (int64_t)(kPnTile / 16) * nbt * kst;
+                    slots += ne;
+                }
             }
         }
     }

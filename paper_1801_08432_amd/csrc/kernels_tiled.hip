@@ -31,6 +31,10 @@
 //            about 6.5 times the useful multiply-adds of the pn part. Adds to
 //            y. With a vector stride NB the same kernel serves the pn part of
 //            the block apply, one vector per workgroup.
+// k_pn2      the float32 one-vector pn kernel: as k_pn, but the two waves of
+//            a workgroup work through pairs of source tiles in step and share
+//            one output row, each owning the destination columns of one
+//            parity, so that six workgroups instead of five fit a CU's LDS.
 #include <hip/hip_runtime.h>
 
 #include "tiled_common.h"
@@ -459,16 +463,252 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
     }
 }
 
-// float: wave-private output rows (plain LDS adds) when they fit; LDS float
-// atomics are far slower than a read and a write
+// ------------------------------------------------------ pn, one shared row
+// One vector. The two waves of a workgroup share one output row, wave
+// w owning the destination columns of parity w. Source tiles go in pairs
+// (steps): wave w contracts tile 2j + w into its R tile, the workgroup
+// synchronises, each wave gathers the step's jumps into its own columns from
+// both R tiles, and a second barrier keeps the R tiles until both gathers are
+// done. One output row per workgroup instead of one per wave: six workgroups
+// (12 waves) fit a CU's LDS instead of five.
+static_assert(kPnWaves == 2, "the shared-row pn kernel splits the destination columns by parity");
+
+struct Pn2Bounds {
+    int e0, e1;   // this wave's list of the step; bit 31 of e0: the step has jumps (either list)
+};
+
+// bounds of steps j0 + lane (past the last step: empty)
+__device__ __forceinline__ void pn2_bounds(Pn2Bounds &pb, int j0, int nsteps, const int32_t *__restrict__ pnp,
+                                           int wid, int lane) {
+    const int st = j0 + lane;
+    const int sc = min(st, nsteps - 1);
+    const int lo = pnp[2 * sc], mid = pnp[2 * sc + 1], hi = pnp[2 * sc + 2];
+    const bool any = st < nsteps && lo != hi;
+    pb.e0 = (wid == 0 ? lo : mid) | (any ? (int)0x80000000u : 0);
+    pb.e1 = wid == 0 ? mid : hi;
+}
+
+template <typename T, int KST>
+struct Pn2Tile {
+    T xv[kPnHalves][KST];
+    uint32_t cr[kPnRounds];
+    int e0, e1;    // this wave's list
+    bool any;      // the step has jumps (uniform across the workgroup)
+    bool mine;     // this wave's tile exists
+};
+
+template <typename T, int KST>
+__device__ __forceinline__ void pn2_fetch(Pn2Tile<T, KST> &b, int j, int wid, int ntiles, int nsteps, Pn2Bounds &pb,
+                                          const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int lane) {
+    if (j > 0 && (j & 63) == 0) pn2_bounds(pb, j, nsteps, pnp, wid, lane);   // uniform, every 64 steps
+    const int e0 = __builtin_amdgcn_readlane(pb.e0, j & 63);
+    b.any = e0 < 0;
+    b.e0 = e0 & 0x7fffffff;
+    b.e1 = __builtin_amdgcn_readlane(pb.e1, j & 63);
+    const int tt = 2 * j + wid;
+    b.mine = tt < ntiles;
+    const int tc = min(tt, ntiles - 1);
+    const unsigned toff = (unsigned)(kPnTile * tc) * (unsigned)sizeof(T);
+#pragma unroll
+    for (int h = 0; h < kPnHalves; ++h)
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks)
+            b.xv[h][ks] = buffer_load<T>(xr, voff[ks] + toff + (unsigned)(16 * h * sizeof(T)), 0);
+#pragma unroll
+    for (int i = 0; i < kPnRounds; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
+}
+
+template <typename T, int NBT, int KST>
+__device__ __forceinline__ void pn2_work(const Pn2Tile<T, KST> &b, const T (&cv)[NBT][KST],
+                                         __amdgpu_buffer_rsrc_t cres, uint32_t null_code, int own, int wid,
+                                         int lane, T *__restrict__ Rw, T *__restrict__ yl) {
+    typedef typename Mma<T>::acc_t acc_t;
+    if (!b.any) return;   // uniform across the workgroup
+    if (b.mine) {
+        acc_t acc[kPnHalves][NBT];
+#pragma unroll
+        for (int h = 0; h < kPnHalves; ++h)
+#pragma unroll
+            for (int bt = 0; bt < NBT; ++bt) acc[h][bt] = Mma<T>::zero();
+#pragma unroll
+        for (int ks = 0; ks < KST; ++ks)
+#pragma unroll
+            for (int h = 0; h < kPnHalves; ++h)
+#pragma unroll
+                for (int bt = 0; bt < NBT; ++bt) acc[h][bt] = Mma<T>::mma(cv[bt][ks], b.xv[h][ks], acc[h][bt]);
+        T *R = Rw + wid * (kPnTile * kPnRStride);
+#pragma unroll
+        for (int h = 0; h < kPnHalves; ++h)
+#pragma unroll
+            for (int bt = 0; bt < NBT; ++bt) Lds<T>::store(R, lane, h, bt, acc[h][bt]);
+    }
+    __syncthreads();
+    // the lane-owned chunk gather of the private-row kernel, from both R tiles
+    // into this wave's columns of the shared row
+    constexpr uint32_t kElem = (1u << kPn2RBits) - 1u, kDst = (1u << kPn2DstBits) - 1u;
+    const int ne = b.e1 - b.e0;
+    const uint32_t ow = (uint32_t)own;
+    T run = 0;
+#pragma unroll
+    for (int i = 0; i < kPnRounds; i += 2) {
+        if (64 * i < ne) {
+            const uint32_t c0 = b.cr[i];
+            const uint32_t c1 = 64 * (i + 1) < ne ? b.cr[i + 1] : null_code;
+            const T v0 = signed_by(Rw[c0 & kElem], c0);
+            const T v1 = signed_by(Rw[c1 & kElem], c1);
+            const uint32_t a0 = (c0 & kPnFlush) ? (c0 >> kPn2RBits) & kDst : ow;
+            const uint32_t a1 = (c1 & kPnFlush) ? (c1 >> kPn2RBits) & kDst : ow;
+            const T s0 = run + v0;
+            const T r1 = (c0 & kPnFlush) ? T(0) : s0;
+            const T s1 = r1 + v1;
+            run = (c1 & kPnFlush) ? T(0) : s1;
+            const T y0 = yl[a0];
+            const T y1 = yl[a1];
+            yl[a0] = y0 + s0;
+            yl[a1] = y1 + s1;
+        }
+    }
+    for (int i = 64 * kPnRounds; i < ne; i += 64) {
+        const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u);
+        run += signed_by(Rw[c & kElem], c);
+        if (c & kPnFlush) {
+            yl[(c >> kPn2RBits) & kDst] += run;
+            run = 0;
+        }
+    }
+    // the R tiles are overwritten by the next step's contraction
+    __syncthreads();
+}
+
+template <typename T, int NBT, int KST>
+__device__ __forceinline__ void pn2_tiles(const PnClass &pc, const T *__restrict__ V, __amdgpu_buffer_rsrc_t xr,
+                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
+                                          int wid, int lane, T *__restrict__ Rw, T *__restrict__ yl) {
+    const int nsteps = (ntiles + 1) >> 1;
+    const int col_l = lane & 15, kq = lane >> 4;
+    unsigned voff[KST];
+    T cv[NBT][KST];
+#pragma unroll
+    for (int ks = 0; ks < KST; ++ks) {
+        const int k = 4 * ks + kq;
+        const bool ok = k < pc.kp;
+        const int code = ok ? pc.ob_code[pc.a0 + k] : 0;
+        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)sizeof(T) : kOutOfRange;
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) {
+            const int B = 16 * bt + col_l;
+            const T v = ok && B < pc.nB ? V[(code >> 1) * pc.nB + B] : (T)0;
+            cv[bt][ks] = (code & 1) ? -v : v;
+        }
+    }
+    const int own = pc.spare + 64 * wid + lane;
+    Pn2Bounds pb;
+    pn2_bounds(pb, 0, nsteps, pnp, wid, lane);
+    // three register sets in rotation, as in the private-row kernel
+    Pn2Tile<T, KST> A, B, C;
+    pn2_fetch<T, KST>(A, 0, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+    pn2_fetch<T, KST>(B, 1, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+    for (int j = 0;; j += 3) {
+        pn2_fetch<T, KST>(C, j + 2, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+        pn2_work<T, NBT, KST>(A, cv, cres, pc.null_code, own, wid, lane, Rw, yl);
+        if (j + 1 >= nsteps) break;
+        pn2_fetch<T, KST>(A, j + 3, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+        pn2_work<T, NBT, KST>(B, cv, cres, pc.null_code, own, wid, lane, Rw, yl);
+        if (j + 2 >= nsteps) break;
+        pn2_fetch<T, KST>(B, j + 4, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+        pn2_work<T, NBT, KST>(C, cv, cres, pc.null_code, own, wid, lane, Rw, yl);
+        if (j + 3 >= nsteps) break;
+    }
+}
+
+template <typename T, int NBT>
+__device__ __forceinline__ void pn2_tiles_k(int ksteps, const PnClass &pc, const T *V, __amdgpu_buffer_rsrc_t xr,
+                                            const int32_t *pnp, __amdgpu_buffer_rsrc_t cres, int ntiles, int wid,
+                                            int lane, T *Rw, T *yl) {
+    switch (ksteps) {
+        case 1: pn2_tiles<T, NBT, 1>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 2: pn2_tiles<T, NBT, 2>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 3: pn2_tiles<T, NBT, 3>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 4: pn2_tiles<T, NBT, 4>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 5: pn2_tiles<T, NBT, 5>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 6: pn2_tiles<T, NBT, 6>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 7: pn2_tiles<T, NBT, 7>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        default: pn2_tiles<T, NBT, 8>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+    }
+}
+
+// Three waves per SIMD (six workgroups per CU, which the LDS allows). Used
+// for float32; in float64 the two R tiles and the barriers made it slower
+// (8.19 against 6.87 ms at pf 5p5n) than the shared row with atomics.
+template <typename T>
+__global__ __launch_bounds__(kPnThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_pn2(
+    DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
+    __shared__ __align__(16) T Rw[kPnWaves * kPnTile * kPnRStride];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *yl = reinterpret_cast<T *>(smem_raw);   // [max_nn + 1 + 64 * kPnWaves]
+    const int ip = TT.order[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int s = P.p_sector[ip];
+    const int nn = P.sec_nn[s];
+    const int64_t base = P.p_pstart[ip];
+    const int nq = P.nq;
+    const int ns2 = TT.n_s2;
+    const __amdgpu_buffer_rsrc_t xr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)sizeof(T)), kBufFlags);
+    const __amdgpu_buffer_rsrc_t cres =
+        __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn2_code, (short)0, (int)(TT.n_pn2_code * 4), kBufFlags);
+    for (int c = tid; c < nn; c += kPnThreads) yl[c] = 0;
+    __syncthreads();
+    bool any = false;
+    PnClass pc;
+    pc.ob_code = P.p.ob_code;
+    pc.ob_base = TT.p_ob_base;
+    pc.null_code = TT.pn2_null;
+    pc.spare = TT.max_nn + 1;
+    for (int q = 0; q < nq; ++q) {
+        const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q], a1 = P.p.ob_ptr[(int64_t)ip * nq + q + 1];
+        if (a0 == a1) continue;   // uniform across the workgroup
+        any = true;
+        const int qn = P.conjq[q];
+        const int nB = P.vq_nb[q];
+        const int nbt = (nB + 15) >> 4;
+        const T *V = TabT<T>::vq(P) + P.vq_off[q];
+        const int nns = P.sec_nn[P.p_sector[P.p.ob_src[a0]]];
+        pc.a0 = a0;
+        pc.kp = a1 - a0;
+        pc.nB = nB;
+        const int ksteps = (pc.kp + 3) >> 2;
+        const int ntiles = (nns + kPnTile - 1) / kPnTile;
+        const int32_t *pnp = TT.pn2_ptr + ((int64_t)s * nq + qn) * ns2 * 2;
+        switch (nbt) {
+            case 1: pn2_tiles_k<T, 1>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+            case 2: pn2_tiles_k<T, 2>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+            case 3: pn2_tiles_k<T, 3>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+            default: pn2_tiles_k<T, 4>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        }
+    }
+    if (!any) return;
+    __syncthreads();
+    for (int c = tid; c < nn; c += kPnThreads) y[base + c] += yl[c];
+}
+
+// float: the one-vector apply shares one output row between the two waves
+// (k_pn2), blocks give each wave a private row (plain LDS adds), when these
+// fit; otherwise, and for double, one shared row with LDS atomics (LDS float
+// atomics are far slower than a read and a write)
 template <typename T, int NB>
 void launch_pn_nb(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_t st) {
     const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1 + 64) * sizeof(T);
     const dim3 grid = NB == 1 ? dim3(d.p.n_sd) : dim3((unsigned)((d.p.n_sd + 7) / 8 * 8 * NB));
     bool priv = false;
     if constexpr (sizeof(T) == 4) {
-        priv = t.pn_priv && lds_priv <= 32768;
-        if (priv) hipLaunchKernelGGL((k_pn<T, true, NB>), grid, dim3(kPnThreads), lds_priv, st, d, t, x, y);
+        priv = t.pn_priv && pn_private_rows_fit(t.max_nn);
+        if (priv && NB == 1)
+            hipLaunchKernelGGL(k_pn2<T>, grid, dim3(kPnThreads), (size_t)(t.max_nn + 1 + 64 * kPnWaves) * sizeof(T),
+                               st, d, t, x, y);
+        else if (priv) hipLaunchKernelGGL((k_pn<T, true, NB>), grid, dim3(kPnThreads), lds_priv, st, d, t, x, y);
     }
     if (!priv)
         hipLaunchKernelGGL((k_pn<T, false, NB>), grid, dim3(kPnThreads), (size_t)(t.max_nn + 1) * sizeof(T), st, d,

@@ -100,7 +100,7 @@ def lib():
         "fotci_trlan_workspace_bytes": (I64, [P, P]),
         "fotci_lanczos_thick_restart": (ctypes.c_int, [P, P, P, P, I64, P, P, P, P, P]),
         "fotci_ham_op_counts": (ctypes.c_int, [P, P, P, P, P]),
-        "fotci_ham_pn_work": (ctypes.c_int, [P, P, P, P]),
+        "fotci_ham_pn_work": (ctypes.c_int, [P, ctypes.c_int32, P, P, P]),
         "fotci_ham_set_pn_private_rows": (ctypes.c_int, [P, ctypes.c_int32]),
         "fotci_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
         "fotci_sym_eigh": (ctypes.c_int, [I32, P, P, P]),
@@ -254,10 +254,11 @@ class Hamiltonian:
         _check(lib().fotci_ham_op_counts(self._h, *[ctypes.byref(x) for x in v]))
         return dict(pp=v[0].value, nn=v[1].value, pn=v[2].value, diag=v[3].value)
 
-    def pn_work(self):
-        """Visited tiles, matrix-core instructions and gather slots of the pn kernel per apply."""
+    def pn_work(self, mode="f32"):
+        """Visited tiles, matrix-core instructions and gather slots of the pn kernel per apply in `mode`."""
         v = [ctypes.c_int64() for _ in range(3)]
-        _check(lib().fotci_ham_pn_work(self._h, *[ctypes.byref(x) for x in v]))
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        _check(lib().fotci_ham_pn_work(self._h, m, *[ctypes.byref(x) for x in v]))
         return dict(tile_visits=v[0].value, mfma_instr=v[1].value, gather_slots=v[2].value)
 
     def set_pn_private_rows(self, enable):

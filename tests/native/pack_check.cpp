@@ -10,6 +10,10 @@
 //   - two chunks of one destination never flush in the same pair of rounds
 //     (the kernel reads the output row for both rounds of a pair before
 //     writing either).
+// The same for the lists of the float32 one-vector kernel, one per (sector,
+// class, pair of source tiles, destination-column parity), whose R element
+// also names the tile of the pair, and whose destinations all have the
+// list's parity (the wave that owns those columns of the shared row).
 // Usage: pack_check Z N (20-state space 2j = 1,3,5,7, 2M = Z + N mod 2).
 #include <cstdio>
 #include <cstdlib>
@@ -38,62 +42,76 @@ int main(int argc, char **argv) {
         return 2;
     }
     const auto &t = h->tt;
-    const uint32_t null_code = (uint32_t)t.max_nn << fotci::kPnRBits;
-    const uint32_t kElem = (1u << fotci::kPnRBits) - 1u, kDst = (1u << fotci::kPnDstBits) - 1u;
-    // expected entries per slot from the jump records
     const auto &cl = j->cls;
-    const int S = (int)b->sectors.size(), nq = cl.nq, nch = std::max(t.n_t16, 1);
+    const int S = (int)b->sectors.size(), nq = cl.nq, nch = std::max(t.n_t16, 1), n2 = std::max(t.n_s2, 1);
     std::vector<int> nsec_to_bsec(b->n.sectors.size(), -1);
     for (int s = 0; s < S; ++s) nsec_to_bsec[b->sectors[s].n_sector] = s;
-    std::map<int64_t, std::multiset<uint32_t>> want;
-    for (const auto &r : j->rec[FOTCI_JUMP_N1]) {
-        const int s = nsec_to_bsec[b->n.sd_sector[r.dst]];
-        if (s < 0) continue;
-        const int64_t slot = ((int64_t)s * nq + cl.class_of[r.label]) * nch + b->n.sd_local[r.src] / fotci::kPnTile;
-        const uint32_t code = (r.phase < 0 ? 0x80000000u : 0u) | ((uint32_t)b->n.sd_local[r.dst] << fotci::kPnRBits) |
-                              (uint32_t)((b->n.sd_local[r.src] % fotci::kPnTile) * fotci::kPnRStride + cl.local_of[r.label]);
-        want[slot].insert(code);
-    }
     long bad = 0, entries = 0, slots = 0;
-    for (size_t sl = 0; sl + 1 < t.pn_ptr.size(); ++sl) {
-        const int e0 = t.pn_ptr[sl], e1 = t.pn_ptr[sl + 1];
-        if ((e1 - e0) % 64) ++bad;
-        const int nr = (e1 - e0) / 64;
-        slots += e1 - e0;
-        std::multiset<uint32_t> got;
-        std::map<uint32_t, std::set<int>> flush_pairs;
-        for (int l = 0; l < 64; ++l) {
-            bool open = false, ended = false;
-            uint32_t cur = 0;
-            for (int r = 0; r < nr; ++r) {
-                const uint32_t c = t.pn_code[e0 + 64 * r + l];
-                if (c == null_code) {
-                    if (open) ++bad;   // a chunk must end in a flush
-                    ended = true;
-                    continue;
-                }
-                if (ended) ++bad;   // a real entry after padding
-                ++entries;
-                got.insert(c & ~fotci::kPnFlush);
-                const uint32_t dst = (c >> fotci::kPnRBits) & kDst;
-                if ((c & kElem) >= (uint32_t)(fotci::kPnTile * fotci::kPnRStride)) ++bad;
-                if (open && dst != cur) ++bad;   // chunks are consecutive per destination
-                open = true;
-                cur = dst;
-                if (c & fotci::kPnFlush) {
-                    if (!flush_pairs[dst].insert(r / 2).second) ++bad;
-                    open = false;
-                }
-            }
-            if (open) ++bad;
+    // pairs = false: per-tile lists; true: the tile-pair, destination-parity lists
+    for (const bool pairs : {false, true}) {
+        const int rbits = pairs ? fotci::kPn2RBits : fotci::kPnRBits;
+        const int dbits = pairs ? fotci::kPn2DstBits : fotci::kPnDstBits;
+        const uint32_t null_code = (uint32_t)t.max_nn << rbits;
+        const uint32_t kElem = (1u << rbits) - 1u, kDst = (1u << dbits) - 1u;
+        const uint32_t n_elem = (uint32_t)((pairs ? 2 : 1) * fotci::kPnTile * fotci::kPnRStride);
+        const auto &ptr = pairs ? t.pn2_ptr : t.pn_ptr;
+        const auto &codes = pairs ? t.pn2_code : t.pn_code;
+        if (ptr.size() != (size_t)S * nq * (pairs ? 2 * n2 : nch) + 1) ++bad;
+        // expected entries per slot from the jump records
+        std::map<int64_t, std::multiset<uint32_t>> want;
+        for (const auto &r : j->rec[FOTCI_JUMP_N1]) {
+            const int s = nsec_to_bsec[b->n.sd_sector[r.dst]];
+            if (s < 0) continue;
+            const int sl = b->n.sd_local[r.src], dl = b->n.sd_local[r.dst], tile = sl / fotci::kPnTile;
+            const int64_t sq = (int64_t)s * nq + cl.class_of[r.label];
+            const int64_t slot = pairs ? (sq * n2 + tile / 2) * 2 + (dl & 1) : sq * nch + tile;
+            const uint32_t elem = (uint32_t)((pairs ? (tile & 1) * fotci::kPnTile * fotci::kPnRStride : 0) +
+                                             (sl % fotci::kPnTile) * fotci::kPnRStride + cl.local_of[r.label]);
+            want[slot].insert((r.phase < 0 ? 0x80000000u : 0u) | ((uint32_t)dl << rbits) | elem);
         }
-        auto it = want.find((int64_t)sl);
-        const std::multiset<uint32_t> empty;
-        if (got != (it == want.end() ? empty : it->second)) ++bad;
+        long ent_here = 0;
+        for (size_t sl = 0; sl + 1 < ptr.size(); ++sl) {
+            const int e0 = ptr[sl], e1 = ptr[sl + 1];
+            if ((e1 - e0) % 64) ++bad;
+            const int nr = (e1 - e0) / 64;
+            slots += e1 - e0;
+            std::multiset<uint32_t> got;
+            std::map<uint32_t, std::set<int>> flush_pairs;
+            for (int l = 0; l < 64; ++l) {
+                bool open = false, ended = false;
+                uint32_t cur = 0;
+                for (int r = 0; r < nr; ++r) {
+                    const uint32_t c = codes[e0 + 64 * r + l];
+                    if (c == null_code) {
+                        if (open) ++bad;   // a chunk must end in a flush
+                        ended = true;
+                        continue;
+                    }
+                    if (ended) ++bad;   // a real entry after padding
+                    ++ent_here;
+                    got.insert(c & ~fotci::kPnFlush);
+                    const uint32_t dst = (c >> rbits) & kDst;
+                    if ((c & kElem) >= n_elem) ++bad;
+                    if (pairs && (dst & 1) != (sl & 1)) ++bad;   // the list's parity
+                    if (open && dst != cur) ++bad;   // chunks are consecutive per destination
+                    open = true;
+                    cur = dst;
+                    if (c & fotci::kPnFlush) {
+                        if (!flush_pairs[dst].insert(r / 2).second) ++bad;
+                        open = false;
+                    }
+                }
+                if (open) ++bad;
+            }
+            auto it = want.find((int64_t)sl);
+            const std::multiset<uint32_t> empty;
+            if (got != (it == want.end() ? empty : it->second)) ++bad;
+        }
+        long want_n = 0;
+        for (const auto &kv : want) want_n += (long)kv.second.size();
+        if (want_n != ent_here) ++bad;
+        entries += ent_here;
     }
-    long want_n = 0;
-    for (const auto &kv : want) want_n += (long)kv.second.size();
-    if (want_n != entries) ++bad;
     printf("Z=%d N=%d: %ld slots, %ld entries, %ld violations\n", Z, N, slots, entries, bad);
     return bad == 0 ? 0 : 1;
 }

@@ -3,8 +3,9 @@
 Block apply: every column of Y = H X, X of shape (dim, n_block) stored
 row-wise, against the oracle's apply_H of that column -- float64 to 1e-12
 relative L2, float32 vectors to 1e-5 (the bars of the one-vector apply) --
-and against the one-vector HIP apply of the same column, which does the same
-per-element arithmetic (1e-15 / 1e-7 relative).
+and against the one-vector HIP apply of the same column (float64: the same
+per-element arithmetic, 1e-15 relative; float32: the same sums in another
+order, 1e-6).
 Block Lanczos: eigenvalues against dense eigh and ARPACK on the oracle's
 operator (1e-9 relative, float64), the float32-vector path against float64
 (1e-5), the seniority closed form with degenerate levels (the multiplicities
@@ -77,7 +78,10 @@ def test_block_apply_f32_matches_oracle(name, nb):
 @pytest.mark.parametrize("mode", ["f64", "f32"])
 @pytest.mark.parametrize("nb", [2, 4, 8])
 def test_block_apply_equals_one_vector_apply(mode, nb):
-    """Per column the block kernels repeat the one-vector kernels' arithmetic."""
+    """Per column the block kernels repeat the one-vector kernels' arithmetic
+    in float64; in float32 the one-vector pn kernel packs its gather lists per
+    pair of tiles and destination parity (shared output row), so the sums run
+    in another order and the columns agree to float32 rounding."""
     w, h, o, prep = setup("pf_4p4n")
     dt = torch.float64 if mode == "f64" else torch.float32
     X = torch.from_numpy(block(h.dim, nb, 60 + nb)).to(DEV, dt)
@@ -87,7 +91,7 @@ def test_block_apply_equals_one_vector_apply(mode, nb):
         y1 = h.apply(X[:, v].contiguous(), mode=mode)
         worst = max(worst, float((Y[:, v] - y1).norm() / y1.norm()))
     _say("[block vs one-vector]", mode, nb, "max rel diff", worst)
-    assert worst <= (1e-15 if mode == "f64" else 1e-7)
+    assert worst <= (1e-15 if mode == "f64" else 1e-6)
 
 
 def test_block_apply_shared_row_policy():

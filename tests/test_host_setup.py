@@ -166,19 +166,22 @@ def test_op_counts_pin():
 
 @pytest.mark.parametrize("name", ["sd_2p2n", "sd_6p6n"])
 def test_pn_work_counts(name):
-    """The pn kernel's work counts, recomputed from the exported jump lists:
-    a (destination row, class, 32-column source tile) is visited when the row
-    has proton jumps of the class and some neutron jump of the conjugate
-    class leaves the tile into the row's neutron sector; it costs
-    2 * ceil(n_B / 16) * ceil(k_p / 4) matrix-core instructions; its gather
-    list is a whole number of 64-entry rounds, at least ceil(entries / 64)
-    (a column's entries may be split over lanes) and at most one round per
-    entry."""
+    """The pn kernels' work counts, recomputed from the exported jump lists.
+    Float64 kernel: a (destination row, class, 32-column source tile) is
+    visited when the row has proton jumps of the class and some neutron jump
+    of the conjugate class leaves the tile into the row's neutron sector; it
+    costs 2 * ceil(n_B / 16) * ceil(k_p / 4) matrix-core instructions; its
+    gather list is a whole number of 64-entry rounds, at least
+    ceil(entries / 64) (a column's entries may be split over lanes) and at
+    most one round per entry. Float32 one-vector kernel: the same per pair of
+    source tiles, both existing tiles of a pair with any jump contracted, and
+    one list per destination-column parity."""
     w = inputs.WORKLOADS[name]
     space = w["two_j"]
     inter, _ = inputs.random_interaction(space, 3)
     h = fotci.Hamiltonian.build(space, w["Z"], w["N"], w["two_M"], inter, upload=False)
-    got = h.pn_work()
+    got = h.pn_work("f64")
+    got32 = h.pn_work("f32")
     b, j = h.basis, h.jumps
     e = b.export()
     ms = ob.m_states(space)
@@ -211,6 +214,23 @@ def test_pn_work_counts(name):
             hi += 64 * len(ent)
     assert got["tile_visits"] == visits and got["mfma_instr"] == mfma
     assert got["gather_slots"] % 64 == 0 and lo <= got["gather_slots"] <= hi
+    pairs, n_src = {}, {}   # (destination sector, delta) -> pair -> destination columns by parity
+    for (src, dst, ph, lab), d in zip(N1.tolist(), dN.tolist()):
+        key = (n_sec[dst], d)
+        n_src[key] = int(e["sectors"][n_sec[src]][5])
+        pairs.setdefault(key, {}).setdefault(n_loc[src] // 64, ([], []))[n_loc[dst] % 2].append(n_loc[dst])
+    visits = mfma = lo = hi = 0
+    for (row, d), k in kp.items():
+        key = (p_sec[row], -d)
+        for pair, lists in pairs.get(key, {}).items():
+            nt = min(2, -(-n_src[key] // 32) - 2 * pair)
+            visits += nt
+            mfma += nt * 2 * (-(-n_ops[-d] // 16)) * (-(-k // 4))
+            for ent in lists:
+                lo += 64 * (-(-len(ent) // 64))
+                hi += 64 * len(ent)
+    assert got32["tile_visits"] == visits and got32["mfma_instr"] == mfma
+    assert got32["gather_slots"] % 64 == 0 and lo <= got32["gather_slots"] <= hi
 
 
 def test_pn_private_rows_argument():
