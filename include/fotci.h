@@ -400,10 +400,12 @@ int fotci_ham_op_counts(const fotci_ham *h, int64_t *ops_pp, int64_t *ops_nn, in
 int fotci_ham_pn_work(const fotci_ham *h, int32_t mode, int64_t *tile_visits, int64_t *mfma_instr,
                       int64_t *gather_slots);
 
-/* Output-row policy of the float32 pn kernel (FOTCI_MODE_F32): 1 (default)
- * gives each wave a private LDS output row when they fit and adds with plain
- * LDS read-modify-write; 0 uses one shared row with LDS atomics. Both give
- * the same sums up to rounding order; the choice changes speed only.
+/* Output-row policy of the float32 pn kernel (FOTCI_MODE_F32, one vector and
+ * blocks): 1 (default) has the two waves of a workgroup take the source tiles
+ * in pairs and own the destination columns of one parity each, so the row is
+ * updated by plain LDS read-modify-write (when the row fits); 0 lets both
+ * waves add to the row with LDS atomics, as the float64 kernel does. Both
+ * give the same sums up to rounding order; the choice changes speed only.
  * FOTCI_EINVAL unless enable is 0 or 1. */
 int fotci_ham_set_pn_private_rows(fotci_ham *h, int32_t enable);
 

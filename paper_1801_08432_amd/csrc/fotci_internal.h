@@ -209,8 +209,9 @@ constexpr uint32_t kPnFlush = 1u << 30;
 constexpr int kPn2RBits = 13;               // 2 * kPnTile * kPnRStride <= 1 << kPn2RBits
 constexpr int kPn2DstBits = 30 - kPn2RBits;
 constexpr int kPnWaves = 2;                 // waves per pn workgroup
-// float32 pn: private output rows (and the one-vector kernel's shared row
-// with its two R tiles) are used when the wave-private rows would fit 32 KiB
+// float32 pn: the row split between the two waves by column parity (k_pn2)
+// is used for rows up to the size at which two wave-private rows would fit
+// 32 KiB (the bound the split kernel was sized against)
 inline bool pn_private_rows_fit(int max_nn) { return (int64_t)kPnWaves * (max_nn + 1 + 64) * 4 <= 32768; }
 
 struct HostTiled {

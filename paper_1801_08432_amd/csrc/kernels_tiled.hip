@@ -22,19 +22,19 @@
 //            source neutron columns jn, K = proton jumps); each wave takes
 //            32-column source tiles, keeps its R tile in LDS, and the neutron
 //            one-body jumps whose source lies in the tile (pre-grouped by
-//            tile, read coalesced) add phase_l R[B_l, jn_l] into the wave's
-//            output row held in LDS. Within a tile every destination column
-//            belongs to one lane, which sums its entries in a register and
-//            updates the output row once.
+//            tile, read coalesced) add phase_l R[B_l, jn_l] into the
+//            workgroup's output row held in LDS. Within a tile every
+//            destination column belongs to one lane, which sums its entries
+//            in a register and adds them to the row with one LDS atomic.
 //            This is the proton-first grouping of sum_{A,B} V_AB P_A X N_B^T:
 //            the contraction over B is dense, so the matrix cores execute
 //            about 6.5 times the useful multiply-adds of the pn part. Adds to
 //            y. With a vector stride NB the same kernel serves the pn part of
-//            the block apply, one vector per workgroup.
-// k_pn2      the float32 one-vector pn kernel: as k_pn, but the two waves of
-//            a workgroup work through pairs of source tiles in step and share
-//            one output row, each owning the destination columns of one
-//            parity, so that six workgroups instead of five fit a CU's LDS.
+//            the block apply, one vector per workgroup. Float64.
+// k_pn2      the float32 pn kernel: as k_pn, but the two waves of a
+//            workgroup work through pairs of source tiles in step, each
+//            owning the destination columns of one parity, and update the row
+//            with plain LDS reads and writes; six workgroups fit a CU.
 #include <hip/hip_runtime.h>
 
 #include "tiled_common.h"
@@ -231,14 +231,12 @@ __device__ __forceinline__ void pn_fetch(PnTile<T, KST> &b, int j, int wid, int 
 }
 
 // Contraction and gather of one fetched tile; cv holds the class's C operand.
-// PRIV: yl is this wave's private output row, updated by plain LDS
-// read-modify-write (two chunks of one destination never flush in one pair of
-// rounds and a wave's LDS operations complete in order); otherwise yl is the
-// workgroup's shared row, updated with one LDS atomic per chunk.
-template <typename T, bool PRIV, int NBT, int KST>
+// yl is the workgroup's shared output row, updated with one LDS atomic per
+// chunk.
+template <typename T, int NBT, int KST>
 __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[NBT][KST],
-                                        __amdgpu_buffer_rsrc_t cres, uint32_t null_code, int spare, int lane,
-                                        T *__restrict__ R, T *__restrict__ yl) {
+                                        __amdgpu_buffer_rsrc_t cres, int lane, T *__restrict__ R,
+                                        T *__restrict__ yl) {
     typedef typename Mma<T>::acc_t acc_t;
     if (b.e0 == b.e1) return;   // uniform: no neutron jump leaves this tile
     acc_t acc[kPnHalves][NBT];
@@ -262,67 +260,26 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
     // The list of a tile is a whole number of 64-entry rounds, so rounds are
     // skipped per wave, not per lane.
     const int ne = b.e1 - b.e0;
-    if constexpr (PRIV) {
-        // A chunk of one destination's entries sits in consecutive rounds of
-        // one lane: the lane sums it in `run` and adds the sum to the output
-        // row at the chunk's flagged last entry. Two chunks of one destination
-        // never flush in the same pair of rounds, so the output-row reads of a
-        // pair go out before either write; a round without a flush reads and
-        // writes the lane's own scratch word past the row.
-        constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
-        const uint32_t own = (uint32_t)(spare + lane);
-        T run = 0;
-        // rounds in pairs: both R reads, then both output-row reads, then
-        // both writes (a round past the list's end takes the null code)
+    // shared row: the lane sums its chunk in a register and adds it with
+    // one LDS atomic at the chunk's flagged last entry
+    constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
+    T run = 0;
 #pragma unroll
-        for (int i = 0; i < kPnRounds; i += 2) {
-            if (64 * i < ne) {
-                const uint32_t c0 = b.cr[i];
-                const uint32_t c1 = 64 * (i + 1) < ne ? b.cr[i + 1] : null_code;
-                const T v0 = signed_by(R[c0 & kElem], c0);
-                const T v1 = signed_by(R[c1 & kElem], c1);
-                const uint32_t a0 = (c0 & kPnFlush) ? (c0 >> kPnRBits) & kDst : own;
-                const uint32_t a1 = (c1 & kPnFlush) ? (c1 >> kPnRBits) & kDst : own;
-                const T s0 = run + v0;
-                const T r1 = (c0 & kPnFlush) ? T(0) : s0;
-                const T s1 = r1 + v1;
-                run = (c1 & kPnFlush) ? T(0) : s1;
-                const T y0 = yl[a0];
-                const T y1 = yl[a1];
-                yl[a0] = y0 + s0;
-                yl[a1] = y1 + s1;
-            }
-        }
-        for (int i = 64 * kPnRounds; i < ne; i += 64) {
-            const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u);
-            run += signed_by(R[c & kElem], c);
-            if (c & kPnFlush) {
-                yl[(c >> kPnRBits) & kDst] += run;
-                run = 0;
-            }
-        }
-    } else {
-        // shared row: the lane sums its chunk in a register and adds it with
-        // one LDS atomic at the chunk's flagged last entry
-        constexpr uint32_t kElem = (1u << kPnRBits) - 1u, kDst = (1u << kPnDstBits) - 1u;
-        T run = 0;
-#pragma unroll
-        for (int i = 0; i < kPnRounds; ++i)
-            if (64 * i < ne) {
-                const uint32_t c = b.cr[i];
-                run += signed_by(R[c & kElem], c);
-                if (c & kPnFlush) {
-                    atomicAdd(&yl[(c >> kPnRBits) & kDst], run);
-                    run = 0;
-                }
-            }
-        for (int i = 64 * kPnRounds; i < ne; i += 64) {
-            const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u);
+    for (int i = 0; i < kPnRounds; ++i)
+        if (64 * i < ne) {
+            const uint32_t c = b.cr[i];
             run += signed_by(R[c & kElem], c);
             if (c & kPnFlush) {
                 atomicAdd(&yl[(c >> kPnRBits) & kDst], run);
                 run = 0;
             }
+        }
+    for (int i = 64 * kPnRounds; i < ne; i += 64) {
+        const uint32_t c = buffer_load_u32(cres, (unsigned)(b.e0 + i + lane) * 4u);
+        run += signed_by(R[c & kElem], c);
+        if (c & kPnFlush) {
+            atomicAdd(&yl[(c >> kPnRBits) & kDst], run);
+            run = 0;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -337,7 +294,7 @@ __device__ __forceinline__ void pn_work(const PnTile<T, KST> &b, const T (&cv)[N
 // tables: lane (col_l, kq) holds C[B = 16 bt + col_l][k = 4 ks + kq] =
 // phase_k V^q[A_k, B] for the matrix cores and the byte offset of its x
 // element in source row k; no workgroup barrier separates the classes.
-template <typename T, bool PRIV, int NBT, int KST, int NB>
+template <typename T, int NBT, int KST, int NB>
 __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict__ V, unsigned goff,
                                          __amdgpu_buffer_rsrc_t xr,
                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
@@ -369,13 +326,13 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
         pn_fetch<T, KST, NB>(B, 1, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
         for (int j = 0;; j += 3) {
             pn_fetch<T, KST, NB>(C, j + 2, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, pc.spare, lane, R, yl);
+            pn_work<T, NBT, KST>(A, cv, cres, lane, R, yl);
             if (wid + W * (j + 1) >= ntiles) break;
             pn_fetch<T, KST, NB>(A, j + 3, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, pc.spare, lane, R, yl);
+            pn_work<T, NBT, KST>(B, cv, cres, lane, R, yl);
             if (wid + W * (j + 2) >= ntiles) break;
             pn_fetch<T, KST, NB>(B, j + 4, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(C, cv, cres, pc.null_code, pc.spare, lane, R, yl);
+            pn_work<T, NBT, KST>(C, cv, cres, lane, R, yl);
             if (wid + W * (j + 3) >= ntiles) break;
         }
     } else {
@@ -384,46 +341,45 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
         pn_fetch<T, KST, NB>(A, 0, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
         for (int j = 0;; j += 2) {
             pn_fetch<T, KST, NB>(B, j + 1, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(A, cv, cres, pc.null_code, pc.spare, lane, R, yl);
+            pn_work<T, NBT, KST>(A, cv, cres, lane, R, yl);
             if (wid + W * (j + 1) >= ntiles) break;
             pn_fetch<T, KST, NB>(A, j + 2, wid, ntiles, pb, voff, goff, xr, pnp, cres, lane);
-            pn_work<T, PRIV, NBT, KST>(B, cv, cres, pc.null_code, pc.spare, lane, R, yl);
+            pn_work<T, NBT, KST>(B, cv, cres, lane, R, yl);
             if (wid + W * (j + 2) >= ntiles) break;
         }
     }
 }
 
-template <typename T, bool PRIV, int NBT, int NB>
+template <typename T, int NBT, int NB>
 __device__ __forceinline__ void pn_tiles_k(int ksteps, const PnClass &pc, const T *V, unsigned goff,
                                            __amdgpu_buffer_rsrc_t xr,
                                            const int32_t *pnp, __amdgpu_buffer_rsrc_t pnc, int ntiles, int wid,
                                            int lane, T *R, T *yl) {
     switch (ksteps) {
-        case 1: pn_tiles<T, PRIV, NBT, 1, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 2: pn_tiles<T, PRIV, NBT, 2, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 3: pn_tiles<T, PRIV, NBT, 3, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 4: pn_tiles<T, PRIV, NBT, 4, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 5: pn_tiles<T, PRIV, NBT, 5, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 6: pn_tiles<T, PRIV, NBT, 6, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        case 7: pn_tiles<T, PRIV, NBT, 7, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
-        default: pn_tiles<T, PRIV, NBT, 8, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 1: pn_tiles<T, NBT, 1, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 2: pn_tiles<T, NBT, 2, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 3: pn_tiles<T, NBT, 3, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 4: pn_tiles<T, NBT, 4, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 5: pn_tiles<T, NBT, 5, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 6: pn_tiles<T, NBT, 6, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        case 7: pn_tiles<T, NBT, 7, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
+        default: pn_tiles<T, NBT, 8, NB>(pc, V, goff, xr, pnp, pnc, ntiles, wid, lane, R, yl); break;
     }
 }
 
-// PRIV: each wave accumulates into its own output row (kPnWaves rows of
-// max_nn + 1 in dynamic LDS, summed at the end); otherwise one shared row
-// with atomics. NB: x and y hold a block of NB vectors stored row-wise
+// The waves of a workgroup accumulate into one shared output row (max_nn + 1
+// in dynamic LDS) with LDS atomics. NB: x and y hold a block of NB vectors stored row-wise
 // (element i of vector v at i * NB + v) and a workgroup handles one vector
 // g0 of one destination row; NB == 1 is the one-vector apply. For NB > 1 the
 // grid is 1-D and the NB workgroups of a row are consecutive slots of one XCD
 // (workgroups are dealt to the 8 XCDs in turn), so the strided loads of the
 // block's vectors share that XCD's L2.
-template <typename T, bool PRIV, int NB>
+template <typename T, int NB>
 __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const T *__restrict__ x,
                                                    T *__restrict__ y) {
     __shared__ __align__(16) T Rw[kPnWaves][kPnTile * kPnRStride];
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *yall = reinterpret_cast<T *>(smem_raw);   // output row(s) [nn]
+    T *yl = reinterpret_cast<T *>(smem_raw);   // output row [max_nn + 1]
 
     int slot = blockIdx.x, g0 = 0;
     if constexpr (NB > 1) {
@@ -448,18 +404,12 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
     const __amdgpu_buffer_rsrc_t cres =
         __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn_code, (short)0, (int)(TT.n_pn_code * 4), kBufFlags);
     T *R = Rw[wid];
-    // one padding column per row, and with private rows 64 scratch words (one per lane)
-    const int ystride = TT.max_nn + 1 + (PRIV ? 64 : 0);
-    T *yl = PRIV ? yall + wid * ystride : yall;
-    for (int w = 0; w < (PRIV ? kPnWaves : 1); ++w)
-        for (int c = tid; c < nn; c += kPnThreads) yall[w * ystride + c] = 0;
+    for (int c = tid; c < nn; c += kPnThreads) yl[c] = 0;
     __syncthreads();
     bool any = false;
     PnClass pc;
     pc.ob_code = P.p.ob_code;
     pc.ob_base = TT.p_ob_base;
-    pc.null_code = TT.pn_null;
-    pc.spare = TT.max_nn + 1;
     for (int q = 0; q < nq; ++q) {
         const int a0 = P.p.ob_ptr[(int64_t)ip * nq + q], a1 = P.p.ob_ptr[(int64_t)ip * nq + q + 1];
         if (a0 == a1) continue;   // uniform across the workgroup
@@ -477,21 +427,15 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
         const int ntiles = (nns + kPnTile - 1) / kPnTile;
         const int32_t *pnp = TT.pn_ptr + pslot;
         switch (nbt) {
-            case 1: pn_tiles_k<T, PRIV, 1, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            case 2: pn_tiles_k<T, PRIV, 2, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            case 3: pn_tiles_k<T, PRIV, 3, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
-            default: pn_tiles_k<T, PRIV, 4, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 1: pn_tiles_k<T, 1, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 2: pn_tiles_k<T, 2, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            case 3: pn_tiles_k<T, 3, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
+            default: pn_tiles_k<T, 4, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, R, yl); break;
         }
     }
     if (!any) return;
     __syncthreads();
-    for (int c = tid; c < nn; c += kPnThreads) {
-        T v = yall[c];
-        if (PRIV)
-#pragma unroll
-            for (int w = 1; w < kPnWaves; ++w) v += yall[w * ystride + c];
-        y[(base + c) * NB + g0] += v;
-    }
+    for (int c = tid; c < nn; c += kPnThreads) y[(base + c) * NB + g0] += yl[c];
 }
 
 // ------------------------------------------------------ pn, one shared row
@@ -528,9 +472,9 @@ struct Pn2Tile {
     bool mine;     // this wave's tile exists
 };
 
-template <typename T, int KST>
+template <typename T, int KST, int NB>
 __device__ __forceinline__ void pn2_fetch(Pn2Tile<T, KST> &b, int j, int wid, int ntiles, int nsteps, Pn2Bounds &pb,
-                                          const unsigned *voff, __amdgpu_buffer_rsrc_t xr,
+                                          const unsigned *voff, unsigned goff, __amdgpu_buffer_rsrc_t xr,
                                           const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int lane) {
     if (j > 0 && (j & 63) == 0) pn2_bounds(pb, j, nsteps, pnp, wid, lane);   // uniform, every 64 steps
     const int e0 = __builtin_amdgcn_readlane(pb.e0, j & 63);
@@ -540,12 +484,12 @@ __device__ __forceinline__ void pn2_fetch(Pn2Tile<T, KST> &b, int j, int wid, in
     const int tt = 2 * j + wid;
     b.mine = tt < ntiles;
     const int tc = min(tt, ntiles - 1);
-    const unsigned toff = (unsigned)(kPnTile * tc) * (unsigned)sizeof(T);
+    const unsigned toff = (unsigned)(kPnTile * tc) * (unsigned)(NB * sizeof(T)) + goff;
 #pragma unroll
     for (int h = 0; h < kPnHalves; ++h)
 #pragma unroll
         for (int ks = 0; ks < KST; ++ks)
-            b.xv[h][ks] = buffer_load<T>(xr, voff[ks] + toff + (unsigned)(16 * h * sizeof(T)), 0);
+            b.xv[h][ks] = buffer_load<T>(xr, voff[ks] + toff + (unsigned)(16 * h * NB * sizeof(T)), 0);
 #pragma unroll
     for (int i = 0; i < kPnRounds; ++i) b.cr[i] = buffer_load_u32(cres, (unsigned)(b.e0 + lane + 64 * i) * 4u);
 }
@@ -575,8 +519,12 @@ __device__ __forceinline__ void pn2_work(const Pn2Tile<T, KST> &b, const T (&cv)
             for (int bt = 0; bt < NBT; ++bt) Lds<T>::store(R, lane, h, bt, acc[h][bt]);
     }
     __syncthreads();
-    // the lane-owned chunk gather of the private-row kernel, from both R tiles
-    // into this wave's columns of the shared row
+    // the lane-owned chunk gather: a chunk of one destination's entries sits
+    // in consecutive rounds of one lane, which sums it and updates the row at
+    // the chunk's flagged last entry; two chunks of one destination never
+    // flush in one pair of rounds, so both rounds' row reads go out before
+    // either write, and a round without a flush reads and writes the lane's
+    // own scratch word past the row. Both R tiles, this wave's columns.
     constexpr uint32_t kElem = (1u << kPn2RBits) - 1u, kDst = (1u << kPn2DstBits) - 1u;
     const int ne = b.e1 - b.e0;
     const uint32_t ow = (uint32_t)own;
@@ -612,8 +560,9 @@ __device__ __forceinline__ void pn2_work(const Pn2Tile<T, KST> &b, const T (&cv)
     __syncthreads();
 }
 
-template <typename T, int NBT, int KST>
-__device__ __forceinline__ void pn2_tiles(const PnClass &pc, const T *__restrict__ V, __amdgpu_buffer_rsrc_t xr,
+template <typename T, int NBT, int KST, int NB>
+__device__ __forceinline__ void pn2_tiles(const PnClass &pc, const T *__restrict__ V, unsigned goff,
+                                          __amdgpu_buffer_rsrc_t xr,
                                           const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
                                           int wid, int lane, T *__restrict__ Rw, T *__restrict__ yl) {
     const int nsteps = (ntiles + 1) >> 1;
@@ -625,7 +574,7 @@ __device__ __forceinline__ void pn2_tiles(const PnClass &pc, const T *__restrict
         const int k = 4 * ks + kq;
         const bool ok = k < pc.kp;
         const int code = ok ? pc.ob_code[pc.a0 + k] : 0;
-        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)sizeof(T) : kOutOfRange;
+        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)(NB * sizeof(T)) : kOutOfRange;
 #pragma unroll
         for (int bt = 0; bt < NBT; ++bt) {
             const int B = 16 * bt + col_l;
@@ -636,49 +585,61 @@ __device__ __forceinline__ void pn2_tiles(const PnClass &pc, const T *__restrict
     const int own = pc.spare + 64 * wid + lane;
     Pn2Bounds pb;
     pn2_bounds(pb, 0, nsteps, pnp, wid, lane);
-    // three register sets in rotation, as in the private-row kernel
+    // three register sets in rotation: tiles j + 1 and j + 2 are in flight
+    // while tile j is worked on
     Pn2Tile<T, KST> A, B, C;
-    pn2_fetch<T, KST>(A, 0, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
-    pn2_fetch<T, KST>(B, 1, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+    pn2_fetch<T, KST, NB>(A, 0, wid, ntiles, nsteps, pb, voff, goff, xr, pnp, cres, lane);
+    pn2_fetch<T, KST, NB>(B, 1, wid, ntiles, nsteps, pb, voff, goff, xr, pnp, cres, lane);
     for (int j = 0;; j += 3) {
-        pn2_fetch<T, KST>(C, j + 2, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+        pn2_fetch<T, KST, NB>(C, j + 2, wid, ntiles, nsteps, pb, voff, goff, xr, pnp, cres, lane);
         pn2_work<T, NBT, KST>(A, cv, cres, pc.null_code, own, wid, lane, Rw, yl);
         if (j + 1 >= nsteps) break;
-        pn2_fetch<T, KST>(A, j + 3, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+        pn2_fetch<T, KST, NB>(A, j + 3, wid, ntiles, nsteps, pb, voff, goff, xr, pnp, cres, lane);
         pn2_work<T, NBT, KST>(B, cv, cres, pc.null_code, own, wid, lane, Rw, yl);
         if (j + 2 >= nsteps) break;
-        pn2_fetch<T, KST>(B, j + 4, wid, ntiles, nsteps, pb, voff, xr, pnp, cres, lane);
+        pn2_fetch<T, KST, NB>(B, j + 4, wid, ntiles, nsteps, pb, voff, goff, xr, pnp, cres, lane);
         pn2_work<T, NBT, KST>(C, cv, cres, pc.null_code, own, wid, lane, Rw, yl);
         if (j + 3 >= nsteps) break;
     }
 }
 
-template <typename T, int NBT>
-__device__ __forceinline__ void pn2_tiles_k(int ksteps, const PnClass &pc, const T *V, __amdgpu_buffer_rsrc_t xr,
+template <typename T, int NBT, int NB>
+__device__ __forceinline__ void pn2_tiles_k(int ksteps, const PnClass &pc, const T *V, unsigned goff,
+                                            __amdgpu_buffer_rsrc_t xr,
                                             const int32_t *pnp, __amdgpu_buffer_rsrc_t cres, int ntiles, int wid,
                                             int lane, T *Rw, T *yl) {
     switch (ksteps) {
-        case 1: pn2_tiles<T, NBT, 1>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-        case 2: pn2_tiles<T, NBT, 2>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-        case 3: pn2_tiles<T, NBT, 3>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-        case 4: pn2_tiles<T, NBT, 4>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-        case 5: pn2_tiles<T, NBT, 5>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-        case 6: pn2_tiles<T, NBT, 6>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-        case 7: pn2_tiles<T, NBT, 7>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-        default: pn2_tiles<T, NBT, 8>(pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 1: pn2_tiles<T, NBT, 1, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 2: pn2_tiles<T, NBT, 2, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 3: pn2_tiles<T, NBT, 3, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 4: pn2_tiles<T, NBT, 4, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 5: pn2_tiles<T, NBT, 5, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 6: pn2_tiles<T, NBT, 6, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        case 7: pn2_tiles<T, NBT, 7, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+        default: pn2_tiles<T, NBT, 8, NB>(pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
     }
 }
 
 // Three waves per SIMD (six workgroups per CU, which the LDS allows). Used
 // for float32; in float64 the two R tiles and the barriers made it slower
 // (8.19 against 6.87 ms at pf 5p5n) than the shared row with atomics.
-template <typename T>
+template <typename T, int NB>
 __global__ __launch_bounds__(kPnThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_pn2(
     DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
     __shared__ __align__(16) T Rw[kPnWaves * kPnTile * kPnRStride];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *yl = reinterpret_cast<T *>(smem_raw);   // [max_nn + 1 + 64 * kPnWaves]
-    const int ip = TT.order[blockIdx.x];
+    // blocks of NB vectors stored row-wise: one vector g0 per workgroup, the
+    // NB workgroups of a row consecutive slots of one XCD (as in k_pn)
+    int slot = blockIdx.x, g0 = 0;
+    if constexpr (NB > 1) {
+        const int xcd = blockIdx.x & 7, s8 = blockIdx.x >> 3;
+        slot = (s8 / NB) * 8 + xcd;
+        g0 = s8 % NB;
+        if (slot >= P.p.n_sd) return;   // uniform: the grid is padded to a multiple of 8 rows
+    }
+    const int ip = TT.order[slot];
+    const unsigned goff = (unsigned)g0 * (unsigned)sizeof(T);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int s = P.p_sector[ip];
@@ -687,7 +648,7 @@ __global__ __launch_bounds__(kPnThreads) __attribute__((amdgpu_waves_per_eu(3)))
     const int nq = P.nq;
     const int ns2 = TT.n_s2;
     const __amdgpu_buffer_rsrc_t xr =
-        __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)sizeof(T)), kBufFlags);
+        __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, (int)(P.dim * (int64_t)(NB * sizeof(T))), kBufFlags);
     const __amdgpu_buffer_rsrc_t cres =
         __builtin_amdgcn_make_buffer_rsrc((void *)TT.pn2_code, (short)0, (int)(TT.n_pn2_code * 4), kBufFlags);
     for (int c = tid; c < nn; c += kPnThreads) yl[c] = 0;
@@ -714,36 +675,33 @@ __global__ __launch_bounds__(kPnThreads) __attribute__((amdgpu_waves_per_eu(3)))
         const int ntiles = (nns + kPnTile - 1) / kPnTile;
         const int32_t *pnp = TT.pn2_ptr + ((int64_t)s * nq + qn) * ns2 * 2;
         switch (nbt) {
-            case 1: pn2_tiles_k<T, 1>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-            case 2: pn2_tiles_k<T, 2>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-            case 3: pn2_tiles_k<T, 3>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
-            default: pn2_tiles_k<T, 4>(ksteps, pc, V, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+            case 1: pn2_tiles_k<T, 1, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+            case 2: pn2_tiles_k<T, 2, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+            case 3: pn2_tiles_k<T, 3, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
+            default: pn2_tiles_k<T, 4, NB>(ksteps, pc, V, goff, xr, pnp, cres, ntiles, wid, lane, Rw, yl); break;
         }
     }
     if (!any) return;
     __syncthreads();
-    for (int c = tid; c < nn; c += kPnThreads) y[base + c] += yl[c];
+    for (int c = tid; c < nn; c += kPnThreads) y[(base + c) * NB + g0] += yl[c];
 }
 
-// float: the one-vector apply shares one output row between the two waves
-// (k_pn2), blocks give each wave a private row (plain LDS adds), when these
-// fit; otherwise, and for double, one shared row with LDS atomics (LDS float
-// atomics are far slower than a read and a write)
+// float: the row split by column parity between the two waves (k_pn2) when
+// it fits; otherwise, and for double, both waves add to the row with LDS
+// atomics (k_pn; LDS float atomics are far slower than a read and a write)
 template <typename T, int NB>
 void launch_pn_nb(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_t st) {
-    const size_t lds_priv = (size_t)kPnWaves * (t.max_nn + 1 + 64) * sizeof(T);
     const dim3 grid = NB == 1 ? dim3(d.p.n_sd) : dim3((unsigned)((d.p.n_sd + 7) / 8 * 8 * NB));
     bool priv = false;
     if constexpr (sizeof(T) == 4) {
         priv = t.pn_priv && pn_private_rows_fit(t.max_nn);
-        if (priv && NB == 1)
-            hipLaunchKernelGGL(k_pn2<T>, grid, dim3(kPnThreads), (size_t)(t.max_nn + 1 + 64 * kPnWaves) * sizeof(T),
-                               st, d, t, x, y);
-        else if (priv) hipLaunchKernelGGL((k_pn<T, true, NB>), grid, dim3(kPnThreads), lds_priv, st, d, t, x, y);
+        if (priv)
+            hipLaunchKernelGGL((k_pn2<T, NB>), grid, dim3(kPnThreads),
+                               (size_t)(t.max_nn + 1 + 64 * kPnWaves) * sizeof(T), st, d, t, x, y);
     }
     if (!priv)
-        hipLaunchKernelGGL((k_pn<T, false, NB>), grid, dim3(kPnThreads), (size_t)(t.max_nn + 1) * sizeof(T), st, d,
-                           t, x, y);
+        hipLaunchKernelGGL((k_pn<T, NB>), grid, dim3(kPnThreads), (size_t)(t.max_nn + 1) * sizeof(T), st, d, t,
+                           x, y);
 }
 
 template <typename T>

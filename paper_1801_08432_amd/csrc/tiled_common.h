@@ -151,8 +151,8 @@ struct PnClass {
     const int32_t *ob_code;   // proton one-body jumps into the row for this class: (local op << 1) | sign
     const int64_t *ob_base;   // their source rows' offsets in x
     int a0, kp, nB;
-    uint32_t null_code;       // padding entry of the gather lists
-    int spare;                // first per-lane scratch word of a private output row
+    uint32_t null_code;       // padding entry of the tile-pair gather lists (k_pn2)
+    int spare;                // first per-lane scratch word past the output row (k_pn2)
 };
 
 // Workgroups are dealt to the 8 XCDs in turn (slot b runs on XCD b % 8). A

@@ -95,8 +95,8 @@ def test_block_apply_equals_one_vector_apply(mode, nb):
 
 
 def test_block_apply_shared_row_policy():
-    """float32 pn kernel with shared output rows (LDS atomics) and with private
-    rows per wave: both match the oracle."""
+    """float32 pn kernel with the output row updated by LDS atomics and with
+    the row split by column parity between the waves: both match the oracle."""
     w, h, o, prep = setup("sd_6p6n")
     X = block(h.dim, 4, 70).astype(np.float32)
     Xt = torch.from_numpy(X).to(DEV)

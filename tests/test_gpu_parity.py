@@ -64,8 +64,9 @@ def test_apply_f32_matches_oracle(name):
 
 
 def test_apply_f32_shared_row_policy():
-    """The float32 pn kernel with one shared LDS output row (atomics) and with
-    private rows per wave: both match the oracle to float32 rounding."""
+    """The float32 pn kernel with the output row updated by LDS atomics and
+    with the row split by column parity between the waves (plain updates):
+    both match the oracle to float32 rounding."""
     w, h, o, prep = setup("sd_6p6n")
     x = inputs.random_vector(h.dim, 13)
     xt = torch.from_numpy(x).float().to(DEV)
