@@ -210,9 +210,11 @@ constexpr int kPn2RBits = 13;               // 2 * kPnTile * kPnRStride <= 1 << 
 constexpr int kPn2DstBits = 30 - kPn2RBits;
 constexpr int kPnWaves = 2;                 // waves per pn workgroup
 // float32 pn: the row split between the two waves by column parity (k_pn2)
-// is used for rows up to the size at which two wave-private rows would fit
-// 32 KiB (the bound the split kernel was sized against)
-inline bool pn_private_rows_fit(int max_nn) { return (int64_t)kPnWaves * (max_nn + 1 + 64) * 4 <= 32768; }
+// is used while its LDS (two R tiles, the row with one padding column and 64
+// scratch words per wave) fits the 64 KiB a workgroup may hold
+inline bool pn_split_row_fits(int max_nn) {
+    return ((int64_t)kPnWaves * kPnTile * kPnRStride + max_nn + 1 + 64 * kPnWaves) * 4 <= 65536;
+}
 
 struct HostTiled {
     std::vector<int32_t> order, nn_ell_E, nn_ell_src, nn_ell_ent, pp_ell_E, pp_ell_src, pp_ell_ent;

@@ -658,7 +658,7 @@ extern "C" int fotci_ham_pn_work_impl(const fotci_ham *h, int32_t mode, int64_t 
     const int ntl = std::max(t.n_t16, 1), ns2 = std::max(t.n_s2, 1);
     const auto &tc = h->tc;
     // the launch's choice of kernel for float32 vectors
-    const bool pairs = mode == FOTCI_MODE_F32 && h->pn_priv && pn_private_rows_fit(t.max_nn);
+    const bool pairs = mode == FOTCI_MODE_F32 && h->pn_priv && pn_split_row_fits(t.max_nn);
     int64_t visits = 0, mfma = 0, slots = 0;
     for (int ip = 0; ip < (int)b->p.sd.size(); ++ip) {
         const int s = tc.p_sector[ip];

@@ -694,7 +694,7 @@ void launch_pn_nb(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStrea
     const dim3 grid = NB == 1 ? dim3(d.p.n_sd) : dim3((unsigned)((d.p.n_sd + 7) / 8 * 8 * NB));
     bool priv = false;
     if constexpr (sizeof(T) == 4) {
-        priv = t.pn_priv && pn_private_rows_fit(t.max_nn);
+        priv = t.pn_priv && pn_split_row_fits(t.max_nn);
         if (priv)
             hipLaunchKernelGGL((k_pn2<T, NB>), grid, dim3(kPnThreads),
                                (size_t)(t.max_nn + 1 + 64 * kPnWaves) * sizeof(T), st, d, t, x, y);
