@@ -188,6 +188,8 @@ struct DevTiled {
     int64_t n_pn2_code;
     uint32_t pn2_null;           // padding code: R element 0, dst col max_nn, not last
     int32_t n_s2;                // tile pairs per sector slot
+    const int8_t *pn_ndiag;      // [n_psd * nq] proton jumps of (row, class) that leave the SD unchanged; they
+                                 // lead the row's list for the class and the pn kernels contract them as one
     uint32_t pn_null;            // padding code
     int32_t n_t16;               // tiles per sector slot (ceil(max nn / kPnTile))
     int32_t kp_pad;              // max proton one-body jumps into a row per class, rounded up to 4
@@ -221,6 +223,7 @@ struct HostTiled {
     std::vector<int64_t> p_ob_base, nn_ell_base, pp_ell_base;
     std::vector<int32_t> rt_sec, rt_r0, ct_sec, ct_c0, pn_ptr, pn2_ptr;
     std::vector<uint32_t> pn_code, pn2_code;
+    std::vector<int8_t> pn_ndiag;
     int n_t16 = 0, n_s2 = 0, kp_pad = 4, max_nn = 0, max_np = 0;
     bool ok = false;
 };

@@ -54,7 +54,8 @@ void build_species_tables(const fotci_jumps *j, int sp, HostSpeciesTables &t) {
         k = e;
     }
     for (int i = 0; i < n_sd; ++i) t.off_rowptr[i + 1] += t.off_rowptr[i];
-    // one-body: by (dst, class, src, local op)
+    // one-body: by (dst, class, src, local op), the jumps with src == dst
+    // (number operators of the occupied orbits) first in their class
     const OpClasses &cl = j->cls;
     const int nq = cl.nq;
     const auto &one = j->rec[sp == 0 ? FOTCI_JUMP_P1 : FOTCI_JUMP_N1];
@@ -63,6 +64,8 @@ void build_species_tables(const fotci_jumps *j, int sp, HostSpeciesTables &t) {
         if (x.dst != y.dst) return x.dst < y.dst;
         int qx = cl.class_of[x.label], qy = cl.class_of[y.label];
         if (qx != qy) return qx < qy;
+        const bool dx = x.src == x.dst, dy = y.src == y.dst;
+        if (dx != dy) return dx;
         if (x.src != y.src) return x.src < y.src;
         return cl.local_of[x.label] < cl.local_of[y.label];
     });
@@ -102,6 +105,18 @@ void build_tiled_tables(fotci_ham *h) {
     t.ok = ok;
     t.p_ob_base.resize(h->tp.ob_src.size());
     for (size_t k = 0; k < h->tp.ob_src.size(); ++k) t.p_ob_base[k] = b->pstart[h->tp.ob_src[k]];
+    // per (row, class): the proton jumps that leave the row's SD unchanged,
+    // which lead its list; the pn kernels contract them as one
+    t.pn_ndiag.assign(h->tp.ob_ptr.size() - 1, 0);
+    for (size_t rq = 0; rq + 1 < h->tp.ob_ptr.size(); ++rq) {
+        const int ip = (int)(rq / (size_t)nq), a0 = h->tp.ob_ptr[rq], a1 = h->tp.ob_ptr[rq + 1];
+        int nd = 0;
+        while (a0 + nd < a1 && h->tp.ob_src[a0 + nd] == ip) ++nd;
+        for (int k = a0 + nd; k < a1; ++k)
+            if (h->tp.ob_src[k] == ip) ok = false;   // not at the front: the merge would be wrong
+        t.pn_ndiag[rq] = (int8_t)std::min(nd, 127);
+        if (nd > 127) ok = false;
+    }
     // ELL tables
     auto ell = [&](const HostSpeciesTables &ts, const SpeciesBasis &sb, bool neutron, std::vector<int64_t> &base,
                    std::vector<int32_t> &E, std::vector<int32_t> &src, std::vector<int32_t> &ent) {
@@ -495,6 +510,7 @@ std::vector<Item> items(fotci_ham *h) {
     add(tt.pn_ptr.data(), tt.pn_ptr.size() * 4, &dt.pn_ptr);
     add(tt.pn_code.data(), tt.pn_code.size() * 4, &dt.pn_code);
     add(tt.pn2_ptr.data(), tt.pn2_ptr.size() * 4, &dt.pn2_ptr);
+    add(tt.pn_ndiag.data(), tt.pn_ndiag.size(), &dt.pn_ndiag);
     add(tt.pn2_code.data(), tt.pn2_code.size() * 4, &dt.pn2_code);
     for (int sp = 0; sp < 2; ++sp) {
         HostSpeciesTables &t = sp == 0 ? h->tp : h->tn;
@@ -667,7 +683,8 @@ extern "C" int fotci_ham_pn_work_impl(const fotci_ham *h, int32_t mode, int64_t 
             if (a0 == a1) continue;
             const int qn = h->j->cls.conj[q];
             const int nbt = (h->vq_nb[q] + 15) / 16;
-            const int kst = (a1 - a0 + 3) / 4;
+            const int nd = t.pn_ndiag[(size_t)ip * nq + q];
+            const int kst = (a1 - a0 - (nd > 1 ? nd - 1 : 0) + 3) / 4;
             const int nns = tc.sec_nn[tc.p_sector[h->tp.ob_src[a0]]];
             const int ntiles = (nns + kPnTile - 1) / kPnTile;
             if (pairs) {

@@ -300,22 +300,9 @@ __device__ __forceinline__ void pn_tiles(const PnClass &pc, const T *__restrict_
                                          const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
                                          int wid, int lane, T *__restrict__ R, T *__restrict__ yl) {
     if (wid >= ntiles) return;
-    const int col_l = lane & 15, kq = lane >> 4;
     unsigned voff[KST];
     T cv[NBT][KST];   // the class's C operand stays in registers for all tiles
-#pragma unroll
-    for (int ks = 0; ks < KST; ++ks) {
-        const int k = 4 * ks + kq;
-        const bool ok = k < pc.kp;
-        const int code = ok ? pc.ob_code[pc.a0 + k] : 0;
-        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)(NB * sizeof(T)) : kOutOfRange;
-#pragma unroll
-        for (int bt = 0; bt < NBT; ++bt) {
-            const int B = 16 * bt + col_l;
-            const T v = ok && B < pc.nB ? V[(code >> 1) * pc.nB + B] : (T)0;
-            cv[bt][ks] = (code & 1) ? -v : v;
-        }
-    }
+    pn_operand<T, NBT, KST, NB>(pc, V, cv, voff, lane);
     PnBounds pb;
     pn_bounds(pb, 0, wid, ntiles, pnp, lane);
     constexpr int W = kPnWaves;
@@ -421,7 +408,8 @@ __global__ __launch_bounds__(kPnThreads) void k_pn(DevHam P, DevTiled TT, const 
         const int nns = P.sec_nn[P.p_sector[P.p.ob_src[a0]]];
         const int64_t pslot = ((int64_t)s * nq + qn) * ntl;
         pc.a0 = a0;
-        pc.kp = a1 - a0;
+        pc.nd = TT.pn_ndiag[(int64_t)ip * nq + q];
+        pc.kp = a1 - a0 - (pc.nd > 1 ? pc.nd - 1 : 0);
         pc.nB = nB;
         const int ksteps = (pc.kp + 3) >> 2;
         const int ntiles = (nns + kPnTile - 1) / kPnTile;
@@ -566,22 +554,9 @@ __device__ __forceinline__ void pn2_tiles(const PnClass &pc, const T *__restrict
                                           const int32_t *__restrict__ pnp, __amdgpu_buffer_rsrc_t cres, int ntiles,
                                           int wid, int lane, T *__restrict__ Rw, T *__restrict__ yl) {
     const int nsteps = (ntiles + 1) >> 1;
-    const int col_l = lane & 15, kq = lane >> 4;
     unsigned voff[KST];
     T cv[NBT][KST];
-#pragma unroll
-    for (int ks = 0; ks < KST; ++ks) {
-        const int k = 4 * ks + kq;
-        const bool ok = k < pc.kp;
-        const int code = ok ? pc.ob_code[pc.a0 + k] : 0;
-        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + k] + col_l) * (unsigned)(NB * sizeof(T)) : kOutOfRange;
-#pragma unroll
-        for (int bt = 0; bt < NBT; ++bt) {
-            const int B = 16 * bt + col_l;
-            const T v = ok && B < pc.nB ? V[(code >> 1) * pc.nB + B] : (T)0;
-            cv[bt][ks] = (code & 1) ? -v : v;
-        }
-    }
+    pn_operand<T, NBT, KST, NB>(pc, V, cv, voff, lane);
     const int own = pc.spare + 64 * wid + lane;
     Pn2Bounds pb;
     pn2_bounds(pb, 0, nsteps, pnp, wid, lane);
@@ -669,7 +644,8 @@ __global__ __launch_bounds__(kPnThreads) __attribute__((amdgpu_waves_per_eu(3)))
         const T *V = TabT<T>::vq(P) + P.vq_off[q];
         const int nns = P.sec_nn[P.p_sector[P.p.ob_src[a0]]];
         pc.a0 = a0;
-        pc.kp = a1 - a0;
+        pc.nd = TT.pn_ndiag[(int64_t)ip * nq + q];
+        pc.kp = a1 - a0 - (pc.nd > 1 ? pc.nd - 1 : 0);
         pc.nB = nB;
         const int ksteps = (pc.kp + 3) >> 2;
         const int ntiles = (nns + kPnTile - 1) / kPnTile;

@@ -150,10 +150,46 @@ __device__ __forceinline__ void pn_bounds(PnBounds &pb, int j0, int wid, int nti
 struct PnClass {
     const int32_t *ob_code;   // proton one-body jumps into the row for this class: (local op << 1) | sign
     const int64_t *ob_base;   // their source rows' offsets in x
-    int a0, kp, nB;
+    int a0, kp, nB;           // kp: contracted jumps, the leading nd >= 2 unchanged-SD jumps counted once
+    int nd;                   // jumps at the front of the list that leave the row's SD unchanged
     uint32_t null_code;       // padding entry of the tile-pair gather lists (k_pn2)
     int spare;                // first per-lane scratch word past the output row (k_pn2)
 };
+
+// A lane's slice of the class operand C[B][k] = phase_k V^q[A_k, B] (lane
+// (col_l, kq) holds B = 16 bt + col_l, k = 4 ks + kq) and the byte offsets of
+// its x elements in source row k. The nd >= 2 jumps that leave the row's SD
+// unchanged (its occupied orbits' number operators, all from the row itself)
+// are one operand row, k = 0, holding the sum of their V rows: x of the row
+// is contracted once instead of nd times. Slot k >= 1 is then jump k + nd - 1.
+template <typename T, int NBT, int KST, int NB>
+__device__ __forceinline__ void pn_operand(const PnClass &pc, const T *__restrict__ V, T (&cv)[NBT][KST],
+                                           unsigned (&voff)[KST], int lane) {
+    const int col_l = lane & 15, kq = lane >> 4;
+    const int shift = pc.nd > 1 ? pc.nd - 1 : 0;
+#pragma unroll
+    for (int ks = 0; ks < KST; ++ks) {
+        const int k = 4 * ks + kq;
+        const bool ok = k < pc.kp;
+        const int kk = k == 0 ? 0 : k + shift;
+        const int code = ok ? pc.ob_code[pc.a0 + kk] : 0;
+        voff[ks] = ok ? (unsigned)(pc.ob_base[pc.a0 + kk] + col_l) * (unsigned)(NB * sizeof(T)) : kOutOfRange;
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) {
+            const int B = 16 * bt + col_l;
+            const bool live = ok && B < pc.nB;
+            T v = live ? V[(code >> 1) * pc.nB + B] : (T)0;
+            v = (code & 1) ? -v : v;
+            if (ks == 0 && k == 0 && live)
+                for (int d = 1; d <= shift; ++d) {
+                    const int cd = pc.ob_code[pc.a0 + d];
+                    const T vd = V[(cd >> 1) * pc.nB + B];
+                    v += (cd & 1) ? -vd : vd;
+                }
+            cv[bt][ks] = v;
+        }
+    }
+}
 
 // Workgroups are dealt to the 8 XCDs in turn (slot b runs on XCD b % 8). A
 // column tile of the pp kernels reads and updates kTile columns (times NB

@@ -175,7 +175,8 @@ def test_pn_work_counts(name):
     ceil(entries / 64) (a column's entries may be split over lanes) and at
     most one round per entry. Float32 one-vector kernel: the same per pair of
     source tiles, both existing tiles of a pair with any jump contracted, and
-    one list per destination-column parity."""
+    one list per destination-column parity. In both, a row's proton jumps
+    that leave its SD unchanged count as one jump (k_p)."""
     w = inputs.WORKLOADS[name]
     space = w["two_j"]
     inter, _ = inputs.random_interaction(space, 3)
@@ -203,9 +204,13 @@ def test_pn_work_counts(name):
     for (src, dst, ph, lab), d in zip(N1.tolist(), dN.tolist()):
         tiles.setdefault((n_sec[dst], d), {}).setdefault(n_loc[src] // 32, []).append(n_loc[dst])
     visits = mfma = lo = hi = 0
-    kp = {}
+    kp, nd = {}, {}
     for (src, dst, ph, lab), d in zip(P1.tolist(), dP.tolist()):
         kp[(dst, d)] = kp.get((dst, d), 0) + 1
+        if src == dst:
+            nd[(dst, d)] = nd.get((dst, d), 0) + 1
+    # the jumps that leave a row's SD unchanged are contracted as one
+    kp = {key: k - max(nd.get(key, 0) - 1, 0) for key, k in kp.items()}
     for (row, d), k in kp.items():
         for ent in tiles.get((p_sec[row], -d), {}).values():
             visits += 1
