@@ -44,7 +44,7 @@ __device__ __forceinline__ Row<T, NB> row_zero() {
 
 // ------------------------------------------------------------ diagonal + nn
 template <typename T, int RT, int NB>
-__global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const T *__restrict__ x,
+__global__ __launch_bounds__(kTS) void k_nn_diag_blk(DevHam P, DevTiled TT, const T *__restrict__ x,
                                                     T *__restrict__ y) {
     typedef Row<T, NB> RowT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
         const RowT *xs = xb + off + (int64_t)r0 * nn;
         __syncthreads();
 #pragma unroll 4
-        for (int idx = tid; idx < RT * nn; idx += kT) {
+        for (int idx = tid; idx < RT * nn; idx += kTS) {
             const int r = idx / nn, c = idx - r * nn;
             // rows past the tile's end load row nr-1 and store zero: no branch around the load
             const RowT v = xs[(int64_t)min(r, nr - 1) * nn + c];
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
 #pragma unroll
         for (int r = 0; r < RT; ++r) dp[r] = r < nr ? dpa[pf + r0 + r] : T(0);
         __syncthreads();
-        for (int c = tid; c < nn; c += kT) {
+        for (int c = tid; c < nn; c += kTS) {
             T acc[RT][NB];
             const T dnc = dn[nf + c];
 #pragma unroll
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag_blk(DevHam P, DevTiled TT, const
 
 // ---------------------------------------------------------------------- pp
 template <typename T, int CT, int NB>
-__global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
+__global__ __launch_bounds__(kTS) void k_pp_blk(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
     typedef Row<T, NB> RowT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     RowT *Xl = reinterpret_cast<RowT *>(smem_raw);   // Xl[r * CT + c]
@@ -133,13 +133,13 @@ __global__ __launch_bounds__(kT) void k_pp_blk(DevHam P, DevTiled TT, const T *_
         const int nc = min(CT, cend - c0);
         __syncthreads();
 #pragma unroll 4
-        for (int idx = tid; idx < np * CT; idx += kT) {
+        for (int idx = tid; idx < np * CT; idx += kTS) {
             const int r = idx / CT, c = idx - r * CT;
             const RowT v = xb[off + (int64_t)r * nn + c0 + min(c, nc - 1)];   // unconditional load
             Xl[idx] = c < nc ? v : row_zero<T, NB>();
         }
         __syncthreads();
-        for (int r = tid; r < np; r += kT) {
+        for (int r = tid; r < np; r += kTS) {
             T acc[CT][NB];
 #pragma unroll
             for (int c = 0; c < CT; ++c)
@@ -179,17 +179,17 @@ template <typename T, int NB>
 void launch_nn_blk(int rt, const DevHam &d, const DevTiled &t, const T *x, T *y, size_t lds, hipStream_t st) {
     if constexpr (4 * NB <= kTile) {
         if (rt == 4) {
-            hipLaunchKernelGGL((k_nn_diag_blk<T, 4, NB>), dim3(t.n_rtiles), dim3(kT), lds, st, d, t, x, y);
+            hipLaunchKernelGGL((k_nn_diag_blk<T, 4, NB>), dim3(t.n_rtiles), dim3(kTS), lds, st, d, t, x, y);
             return;
         }
     }
     if constexpr (2 * NB <= kTile) {
         if (rt == 2) {
-            hipLaunchKernelGGL((k_nn_diag_blk<T, 2, NB>), dim3(t.n_rtiles), dim3(kT), lds, st, d, t, x, y);
+            hipLaunchKernelGGL((k_nn_diag_blk<T, 2, NB>), dim3(t.n_rtiles), dim3(kTS), lds, st, d, t, x, y);
             return;
         }
     }
-    hipLaunchKernelGGL((k_nn_diag_blk<T, 1, NB>), dim3(t.n_rtiles), dim3(kT), lds, st, d, t, x, y);
+    hipLaunchKernelGGL((k_nn_diag_blk<T, 1, NB>), dim3(t.n_rtiles), dim3(kTS), lds, st, d, t, x, y);
 }
 
 template <typename T, int NB>
@@ -197,17 +197,17 @@ void launch_pp_blk(int ct, const DevHam &d, const DevTiled &t, const T *x, T *y,
     const dim3 grid(pp_grid(t.n_ctiles, pp_line_group<T, NB>()));
     if constexpr (4 * NB <= kTile) {
         if (ct == 4) {
-            hipLaunchKernelGGL((k_pp_blk<T, 4, NB>), grid, dim3(kT), lds, st, d, t, x, y);
+            hipLaunchKernelGGL((k_pp_blk<T, 4, NB>), grid, dim3(kTS), lds, st, d, t, x, y);
             return;
         }
     }
     if constexpr (2 * NB <= kTile) {
         if (ct == 2) {
-            hipLaunchKernelGGL((k_pp_blk<T, 2, NB>), grid, dim3(kT), lds, st, d, t, x, y);
+            hipLaunchKernelGGL((k_pp_blk<T, 2, NB>), grid, dim3(kTS), lds, st, d, t, x, y);
             return;
         }
     }
-    hipLaunchKernelGGL((k_pp_blk<T, 1, NB>), grid, dim3(kT), lds, st, d, t, x, y);
+    hipLaunchKernelGGL((k_pp_blk<T, 1, NB>), grid, dim3(kTS), lds, st, d, t, x, y);
 }
 
 template <typename T, int NB>

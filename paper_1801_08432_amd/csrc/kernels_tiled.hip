@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kT) void k_ell_values(const int32_t *__restrict__ s
 // ------------------------------------------------------------ diagonal + nn
 // RT rows are staged per pass (RT * max_nn * sizeof(T) <= kLdsTile).
 template <typename T, int RT>
-__global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
+__global__ __launch_bounds__(kTS) void k_nn_diag(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Xl = reinterpret_cast<T *>(smem_raw);   // Xl[c * RT + r]
     const int tid = threadIdx.x;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
         const T *xs = x + off + (int64_t)r0 * nn;
         __syncthreads();
 #pragma unroll 4
-        for (int idx = tid; idx < RT * nn; idx += kT) {
+        for (int idx = tid; idx < RT * nn; idx += kTS) {
             const int r = idx / nn, c = idx - r * nn;
             // rows past the tile's end load row nr-1 and store zero: no branch around the load
             const T v = xs[(int64_t)min(r, nr - 1) * nn + c];
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
 #pragma unroll
         for (int r = 0; r < RT; ++r) dp[r] = r < nr ? dpa[pf + r0 + r] : T(0);
         __syncthreads();
-        for (int c = tid; c < nn; c += kT) {
+        for (int c = tid; c < nn; c += kTS) {
             T acc[RT];
             const T dnc = dn[nf + c];
 #pragma unroll
@@ -110,15 +110,15 @@ __global__ __launch_bounds__(kT) void k_nn_diag(DevHam P, DevTiled TT, const T *
 
 // ---------------------------------------------------------------------- pp
 // CT columns are staged per pass (max_np * CT * sizeof(T) <= kLdsTile).
-// STAGED (float32, np <= kPpRows * kT): each thread keeps the sums of its rows
+// STAGED (float32, np <= kPpRows * kTS): each thread keeps the sums of its rows
 // in registers, the slab is then overwritten with them, and y is updated in a
 // second pass in which consecutive threads cover a row's CT columns (the
 // row-per-thread update touches 64 rows per wave instruction: 0.347 against
 // 0.268 ms at pf 5p5n). Float64 keeps the row-per-thread update (twice the
 // registers per row; the staged form ran at 1.87 against 0.68 ms).
-constexpr int kPpRows = 8;
+constexpr int kPpRows = 4;   // rows per thread of the staged pp update
 template <typename T, int CT, bool STAGED>
-__global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
+__global__ __launch_bounds__(kTS) void k_pp(DevHam P, DevTiled TT, const T *__restrict__ x, T *__restrict__ y) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Xl = reinterpret_cast<T *>(smem_raw);   // Xl[r * CT + c]
     const int tid = threadIdx.x;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
         const int nc = min(CT, cend - c0);
         __syncthreads();
 #pragma unroll 4
-        for (int idx = tid; idx < np * CT; idx += kT) {
+        for (int idx = tid; idx < np * CT; idx += kTS) {
             const int r = idx / CT, c = idx - r * CT;
             const T v = x[off + (int64_t)r * nn + c0 + min(c, nc - 1)];   // unconditional load
             Xl[r * CT + (c ^ slab_swz<T, CT>(r))] = c < nc ? v : T(0);
@@ -161,22 +161,22 @@ __global__ __launch_bounds__(kT) void k_pp(DevHam P, DevTiled TT, const T *__res
             T acc[kPpRows][CT];
 #pragma unroll
             for (int i = 0; i < kPpRows; ++i)
-                if (tid + i * kT < np) walk(tid + i * kT, acc[i]);
+                if (tid + i * kTS < np) walk(tid + i * kTS, acc[i]);
             __syncthreads();   // every read of the slab is done
 #pragma unroll
             for (int i = 0; i < kPpRows; ++i) {
-                const int r = tid + i * kT;
+                const int r = tid + i * kTS;
                 if (r < np)
 #pragma unroll
                     for (int c = 0; c < CT; ++c) Xl[r * CT + c] = acc[i][c];
             }
             __syncthreads();
-            for (int idx = tid; idx < np * CT; idx += kT) {
+            for (int idx = tid; idx < np * CT; idx += kTS) {
                 const int r = idx / CT, c = idx - r * CT;
                 if (c < nc) y[off + (int64_t)r * nn + c0 + c] += Xl[idx];
             }
         } else {
-            for (int r = tid; r < np; r += kT) {
+            for (int r = tid; r < np; r += kTS) {
                 T acc[CT];
                 walk(r, acc);
                 T *yr = y + off + (int64_t)r * nn + c0;
@@ -686,28 +686,28 @@ void launch_all(const DevHam &d, const DevTiled &t, const T *x, T *y, hipStream_
     const int rt = pick_tile(t.max_nn, sizeof(T));
     const size_t lds_nn = (size_t)rt * t.max_nn * sizeof(T);
     switch (rt) {
-        case 8: hipLaunchKernelGGL((k_nn_diag<T, 8>), dim3(t.n_rtiles), dim3(kT), lds_nn, st, d, t, x, y); break;
-        case 4: hipLaunchKernelGGL((k_nn_diag<T, 4>), dim3(t.n_rtiles), dim3(kT), lds_nn, st, d, t, x, y); break;
-        case 2: hipLaunchKernelGGL((k_nn_diag<T, 2>), dim3(t.n_rtiles), dim3(kT), lds_nn, st, d, t, x, y); break;
-        default: hipLaunchKernelGGL((k_nn_diag<T, 1>), dim3(t.n_rtiles), dim3(kT), lds_nn, st, d, t, x, y); break;
+        case 8: hipLaunchKernelGGL((k_nn_diag<T, 8>), dim3(t.n_rtiles), dim3(kTS), lds_nn, st, d, t, x, y); break;
+        case 4: hipLaunchKernelGGL((k_nn_diag<T, 4>), dim3(t.n_rtiles), dim3(kTS), lds_nn, st, d, t, x, y); break;
+        case 2: hipLaunchKernelGGL((k_nn_diag<T, 2>), dim3(t.n_rtiles), dim3(kTS), lds_nn, st, d, t, x, y); break;
+        default: hipLaunchKernelGGL((k_nn_diag<T, 1>), dim3(t.n_rtiles), dim3(kTS), lds_nn, st, d, t, x, y); break;
     }
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[1], st), "event");
     const int ct = pick_tile(t.max_np, sizeof(T));
     const size_t lds_pp = (size_t)ct * t.max_np * sizeof(T);
     const dim3 gpp(pp_grid(t.n_ctiles, kPpRunLines * pp_line_group<T, 1>()));
-    if (sizeof(T) == 4 && t.max_np <= kPpRows * kT) {
+    if (sizeof(T) == 4 && t.max_np <= kPpRows * kTS) {
         switch (ct) {
-            case 8: hipLaunchKernelGGL((k_pp<T, 8, true>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
-            case 4: hipLaunchKernelGGL((k_pp<T, 4, true>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
-            case 2: hipLaunchKernelGGL((k_pp<T, 2, true>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
-            default: hipLaunchKernelGGL((k_pp<T, 1, true>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
+            case 8: hipLaunchKernelGGL((k_pp<T, 8, true>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
+            case 4: hipLaunchKernelGGL((k_pp<T, 4, true>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
+            case 2: hipLaunchKernelGGL((k_pp<T, 2, true>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
+            default: hipLaunchKernelGGL((k_pp<T, 1, true>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
         }
     } else {
         switch (ct) {
-            case 8: hipLaunchKernelGGL((k_pp<T, 8, false>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
-            case 4: hipLaunchKernelGGL((k_pp<T, 4, false>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
-            case 2: hipLaunchKernelGGL((k_pp<T, 2, false>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
-            default: hipLaunchKernelGGL((k_pp<T, 1, false>), gpp, dim3(kT), lds_pp, st, d, t, x, y); break;
+            case 8: hipLaunchKernelGGL((k_pp<T, 8, false>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
+            case 4: hipLaunchKernelGGL((k_pp<T, 4, false>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
+            case 2: hipLaunchKernelGGL((k_pp<T, 2, false>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
+            default: hipLaunchKernelGGL((k_pp<T, 1, false>), gpp, dim3(kTS), lds_pp, st, d, t, x, y); break;
         }
     }
     if (ev) hip_check(hipEventRecord((hipEvent_t)ev[2], st), "event");

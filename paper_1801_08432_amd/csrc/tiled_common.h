@@ -15,6 +15,12 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;      // threads per workgroup (4 waves)
+// Threads of the nn and pp workgroups (one vector and blocks): 8 waves share
+// a staged slab (three slabs of 53 KB fit a CU, so 24 waves), which hides the
+// ELL loads' latency better than 4 waves (f32 nn 0.253 -> 0.205 ms, pp 0.285
+// -> 0.249 ms at pf 5p5n; blocks of 4: nn 0.99 -> 0.89 ms, pp 1.33 -> 1.29 ms)
+// or 16 (0.220 / 0.270 ms).
+constexpr int kTS = 512;
 constexpr int kTile = 8;     // rows (nn kernel) / columns (pp kernel) per tile
 // Bytes of LDS for a staged tile: at most half of a CU's 160 KiB, so that two
 // workgroups share a CU (a 106 KiB float64 slab left one per CU, 4 waves,
