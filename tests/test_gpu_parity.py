@@ -132,6 +132,13 @@ def test_apply_edge_cases(space, Z, N, two_M, par, opar):
         y = h.apply(torch.from_numpy(x).to(DEV), mode=mode).cpu().numpy()
         nrm = max(np.linalg.norm(ref), 1e-300)
         assert np.linalg.norm(y - ref) <= 1e-12 * nrm + 1e-300
+    # the float32 path (split-row pn kernel, staged pp) on the same shapes,
+    # against the oracle applied to the float32-rounded vector
+    x32 = x.astype(np.float32)
+    ref32 = oh.dense_h(o, inter) @ x32.astype(np.float64) if o.dim <= 3000 else \
+        of.apply_h(of.Prepared(o), inter, x32.astype(np.float64))
+    y32 = h.apply(torch.from_numpy(x32).to(DEV), mode="f32").double().cpu().numpy()
+    assert np.linalg.norm(y32 - ref32) <= 1e-5 * np.linalg.norm(ref32) + 1e-30
 
 
 def test_lanczos_f64_matches_dense_eigh():
